@@ -1,0 +1,60 @@
+"""Pins of the IDA oracle (Section VI, eqs 13, 15, 25, 28).
+
+With the identity denoiser x^{t+1} = x^t + A* z^t, so every measured
+coefficient c of x follows the scalar recurrence (y its measurement,
+alpha = 1/D_F):
+    z^t = y - c^t + alpha z^{t-1},   c^{t+1} = c^t + z^t,   c^0 = 0, z^{-1} = 0.
+Worked by hand, c^t / y for t = 1..8 is
+    alpha = 1/2 : 1, 1.5, 1.25, 0.875, 0.8125, 0.96875, 1.078125, ...
+    alpha = 1   : 1, 2, 2, 1, 0, 0, 1, 2       (period 6: D_F = 1 oscillates)
+    alpha = 0   : 1, 1, 1, ...                   (ISTA fixed point I_o)
+and z^t / y for alpha = 1/2 is 1, 0.5, -0.25, -0.375, -0.0625, 0.15625.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import abcs, ida
+
+HALF = [1.0, 1.5, 1.25, 0.875, 0.8125, 0.96875, 1.078125]
+ONE = [1.0, 2.0, 2.0, 1.0, 0.0, 0.0, 1.0, 2.0]
+Z_HALF = [1.0, 0.5, -0.25, -0.375, -0.0625, 0.15625]
+
+
+@pytest.fixture(scope="module")
+def case():
+    img = synth.synth_image(31, 64, 48)
+    k, _, y = abcs.encode(img, 16, 0.25, abcs.BBV)
+    return img, k, y
+
+
+@pytest.mark.parametrize("damping,ratios", [(2.0, HALF), (1.0, ONE), (math.inf, [1.0] * 5)])
+def test_identity_denoiser_recurrence(case, damping, ratios):
+    img, k, y = case
+    for t, ratio in enumerate(ratios, start=1):
+        x, _ = ida.ida(y, k, 16, 64, 48, t, damping)
+        c = abcs.sense_op(x, 16, k)
+        assert np.max(np.abs(c - ratio * y)) < 1e-8 * np.max(np.abs(y))
+
+
+def test_sigma_trace_and_first_iterate(case):
+    img, k, y = case
+    trace = []
+    _, sig = ida.ida(y, k, 16, 64, 48, 6, 2.0, trace=trace)
+    base = math.sqrt(float(np.sum(y * y)) / y.size)
+    assert np.allclose(sig, [abs(r) * base for r in Z_HALF], rtol=1e-9)
+    # v^0 = A* y = I_o, the real-time reconstruction
+    assert np.max(np.abs(trace[0][1] - abcs.reconstruct(y, 16, k, 64, 48))) < 1e-9
+
+
+def test_iterates_stay_in_measured_subspace(case):
+    img, k, y = case
+    x, _ = ida.ida(y, k, 16, 64, 48, 5, 2.0)
+    C = abcs.block_dct(abcs.to_blocks(x, 16), abcs.dct_matrix(16))
+    zz = abcs.zigzag(16)
+    for i, ki in enumerate(k):
+        for z in range(int(ki), 256):
+            r, c = zz[z]
+            assert abs(C[i, r, c]) < 1e-8
