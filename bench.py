@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of adaptive block compressive sensing on one MI355X.
+
+Workload (one step): a batch of 64 synthetic 512x512 uint8 greyscale images
+(seeds 1000..1063), B = 16, both budget estimators (AL-DCT-BBV and
+AL-DCT-DD) at subrates 0.1, 0.2, 0.3, 0.4, 0.5 - 640 image encodings in one
+plan - run through phase-1 statistics + budget apportionment (abcs_budget),
+phase-2 sensing (abcs_sense) and the masked inverse 2D-DCT decoder
+(abcs_reconstruct), float32.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: Mpixel/s over the whole step, the roofline of the
+dominant kernel (HIP events on the launch stream) and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SEEDS = list(range(1000, 1064))
+SUBRATES = (0.1, 0.2, 0.3, 0.4, 0.5)
+METHODS = ("bbv", "dd")
+H = W = 512
+B = 16
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_images():
+    import numpy as np
+    import synth
+    return np.stack([synth.synth_image(s, H, W) for s in SEEDS])
+
+
+def entries():
+    out = []
+    for m in METHODS:
+        for cr in SUBRATES:
+            for i in range(len(SEEDS)):
+                out.append(dict(height=H, width=W, row_pitch=W, block=B, subrate=cr, method=m,
+                                pixel_offset=i * H * W))
+    return out
+
+
+def algorithmic_bytes(plan, kind):
+    """Bytes each launch must move at least, from the plan's sizes.
+
+    reconstruct: read y (4 B per coefficient), k (4 B/block), offsets
+                 (8 B/block); write the decoded image (4 B/pixel).
+    sense:       read the pixels (1 B/pixel), k, offsets; write y.
+    """
+    if kind == "reconstruct":
+        return 4 * plan.meas + 12 * plan.blocks + 4 * plan.pixels
+    if kind == "sense":
+        return plan.pixels + 12 * plan.blocks + 4 * plan.meas
+    raise ValueError(kind)
+
+
+def cpu_baseline(images, n_images, deadline_s=30.0):
+    """The FP64 oracle (budget + sensing + decoding) on the first n_images of
+    the batch at every (estimator, subrate) pair; single-threaded numpy."""
+    from oracle import abcs as orc
+    t0 = time.perf_counter()
+    done_px = 0
+    done = 0
+    for i in range(n_images):
+        for m in METHODS:
+            for cr in SUBRATES:
+                k, _, y = orc.encode(images[i], B, cr, orc.METHOD_NAMES[m])
+                orc.reconstruct(y, B, k, H, W)
+                done_px += H * W
+                done += 1
+        if time.perf_counter() - t0 > deadline_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=done_px / dt / 1e6, unit="Mpixel/s", cores=1, kind="oracle",
+                sample=f"{done} of 640 image encodings (first {done // 10} images x 2 estimators x 5 subrates), "
+                       f"budget+sense+inverse DCT in float64 numpy, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-images", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batch would shard by "
+              f"image across GPUs with no communication, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2001_09632_amd as g
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("generating images")
+    images = make_images()
+    px = torch.from_numpy(images.reshape(-1)).to(dev)
+    plan = g.Plan(entries())
+    k = torch.empty(plan.blocks, dtype=torch.int32, device=dev)
+    off = torch.empty(plan.blocks, dtype=torch.int64, device=dev)
+    stat = torch.empty(plan.blocks, dtype=torch.int32, device=dev)
+    y = torch.empty(plan.meas, dtype=torch.float32, device=dev)
+    out = torch.empty(plan.pixels, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        g.budget(plan, px, k, off, stat, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        g.sense(plan, px, k, off, y, stream)
+        if ev is not None:
+            ev[2].record(stream)
+        g.reconstruct(plan, y, k, off, out, stream)
+        if ev is not None:
+            ev[3].record(stream)
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    log("timing")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_budget = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    ms_sense = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ms_recon = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+
+    pixels_per_step = plan.pixels
+    value = pixels_per_step * args.steps / elapsed / 1e6
+    kernels = {"sense": ms_sense, "reconstruct": ms_recon}
+    dom = max(kernels, key=kernels.get)
+    ach = algorithmic_bytes(plan, dom) / (kernels[dom] * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+    per_kernel_ms = dict(budget=round(ms_budget, 4), sense=round(ms_sense, 4), reconstruct=round(ms_recon, 4))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        cpu = cpu_baseline(images, args.cpu_images)
+
+    rec = {
+        "metric": "Mpixel/s ABCS sense+iDCT; IDA images/s at matched PSNR, learned vs plain",
+        "value": round(value, 1),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "64 synthetic 512x512 uint8 images, B=16, AL-DCT-BBV and AL-DCT-DD at C_R "
+                               "0.1/0.2/0.3/0.4/0.5 (640 encodings per step): budget + sense + masked inverse DCT",
+                   "images": len(SEEDS), "height": H, "width": W, "block": B, "encodings_per_step": plan.n,
+                   "pixels_per_step": pixels_per_step},
+        "per_kernel_ms": per_kernel_ms,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

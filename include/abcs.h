@@ -1,0 +1,162 @@
+/*
+ * abcs.h - C ABI of the MI355X (gfx950) adaptive block compressive sensing
+ * library: AL-DCT-BBV / AL-DCT-DD / L-DCT-ZZ sensing with per-block DCT
+ * coefficient budgets, the masked inverse 2D-DCT decoder, and IDA
+ * post-processing.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers named d_* are device pointers (HIP global memory on the device
+ *    the plan was created on); pointers named h_* are host pointers.  The
+ *    caller owns and allocates every buffer; the library never frees caller
+ *    memory.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
+ *    that takes a stream only enqueues work on it and returns without waiting
+ *    for the device.
+ *  - Every call returns an abcs_status.  Arguments are checked on the host
+ *    before anything is enqueued; on an error return no device memory has
+ *    been written and abcs_last_error() describes the problem.  A failed HIP
+ *    launch returns ABCS_EHIP.  Nothing throws or aborts across this ABI.
+ *  - Thread safety: plans are immutable after creation and may be used from
+ *    several host threads; calls that overlap on the device must not share
+ *    output buffers.
+ *
+ * Geometry (eq 20; Alg 1 and Alg 2 step 1): an H x W image is cropped to
+ * H' = B floor(H/B) rows and W' = B floor(W/B) columns and cut into
+ * n_B = (H'/B)(W'/B) blocks numbered in raster order.  The cropped image
+ * holds N = H' W' pixels and the image's measurement budget is
+ * M = floor(C_R N) with C_R the subrate and C_F = N / M the compression factor.
+ *
+ * Batch layout: per-block arrays (k, offsets, stat) hold the blocks of image
+ * 0, then image 1, ...; y holds every block's DCT coefficients in zigzag order,
+ * block after block and image after image; decoded images are H' x W' float32
+ * arrays with row pitch W', stored one after the other.  abcs_plan_create
+ * computes these offsets.
+ */
+#ifndef ABCS_H
+#define ABCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Budget rule for an image. */
+typedef enum abcs_method {
+  ABCS_ZZ = 0,  /* L-DCT-ZZ: floor(B^2 C_R) lowest zigzag coefficients per
+                   block (Section IV; eq 26).                                */
+  ABCS_BBV = 1, /* AL-DCT-BBV (Algorithm 1; eqs 16-19, 21, 22).  Needs
+                   C_R <= 0.5 (L = floor(C_F) >= 2); with n_S = floor(B/L) = 0
+                   it reverts to L-DCT-ZZ.                                   */
+  ABCS_DD = 2   /* AL-DCT-DD (Algorithm 2; eq 23; Table 1).                  */
+} abcs_method;
+
+typedef enum abcs_status {
+  ABCS_OK = 0,
+  ABCS_EINVAL = -1,      /* bad argument: null pointer, size, alignment     */
+  ABCS_EDOMAIN = -2,     /* parameters outside the method's domain          */
+  ABCS_EUNSUPPORTED = -3,/* valid but not supported by this build (e.g. B)  */
+  ABCS_ENOSPACE = -4,    /* a caller buffer or workspace is too small       */
+  ABCS_EHIP = -5         /* a HIP runtime call or kernel launch failed      */
+} abcs_status;
+
+/* IDA denoisers (Section VI-4). */
+typedef enum abcs_denoiser {
+  ABCS_DENOISE_IDENTITY = 0, /* D(v) = v: the loop without a denoiser        */
+  ABCS_DENOISE_BM3D = 1,     /* plain BM3D (Dabov et al., ref [22])          */
+  ABCS_DENOISE_CNN = 2       /* learned 8-layer 3x3 CNN (parameters passed)  */
+} abcs_denoiser;
+
+/* One image of a batch.  The caller fills the first block of fields;
+ * abcs_plan_create fills the layout fields of its own copy, which
+ * abcs_plan_image returns. */
+typedef struct abcs_image {
+  int32_t height;        /* H, rows of the uncropped image                   */
+  int32_t width;         /* W, columns of the uncropped image                */
+  int32_t row_pitch;     /* bytes between rows of the uint8 pixels; >= W,
+                            multiple of 4                                    */
+  int32_t block;         /* B: 16 (8 and 32 are reserved, EUNSUPPORTED)      */
+  double subrate;        /* C_R in (0, 1]                                    */
+  int32_t method;        /* abcs_method                                      */
+  int32_t reserved;      /* must be 0                                        */
+  int64_t pixel_offset;  /* byte offset of pixel (0,0) in the pixel buffer;
+                            multiple of 4.  Several descriptors may name the
+                            same pixels (e.g. one image at several C_R).      */
+  /* ---- filled by abcs_plan_create ---- */
+  int64_t block_offset;  /* first block of this image in per-block arrays    */
+  int64_t meas_offset;   /* first coefficient of this image in y             */
+  int64_t out_offset;    /* first pixel of this image in decoded buffers     */
+  int64_t n_meas;        /* DCT coefficients this image puts in y:
+                            ZZ: n_B floor(B^2 C_R); BBV: M - M_BBV; DD: M    */
+  int32_t cropped_height;/* H'                                               */
+  int32_t cropped_width; /* W'                                               */
+} abcs_image;
+
+typedef struct abcs_plan abcs_plan; /* opaque */
+
+/* Validate a batch, compute its layout and upload its descriptor tables to the
+ * current HIP device (allocates device memory once; not for the hot path).
+ * h_imgs: n descriptors (n >= 0), read only.  On success *out receives a plan
+ * that must be released with abcs_plan_destroy.
+ * Errors: EINVAL (null pointer, n < 0, pitch/offset/alignment), EDOMAIN
+ * (C_R outside (0,1], no whole block, M = 0, BBV with C_R > 0.5, BBV samples
+ * exceeding M), EUNSUPPORTED (B != 16), EHIP. */
+int abcs_plan_create(const abcs_image* h_imgs, int n, abcs_plan** out);
+void abcs_plan_destroy(abcs_plan* plan);
+
+/* Totals of a plan: number of blocks (length of k, offsets, stat), number of
+ * DCT coefficients (length of y) and decoded pixels (length of an image
+ * buffer).  Any pointer may be NULL. */
+int abcs_plan_totals(const abcs_plan* plan, int64_t* h_blocks, int64_t* h_meas,
+                     int64_t* h_pixels);
+/* Copy descriptor i, with its layout fields filled, into *h_out. */
+int abcs_plan_image(const abcs_plan* plan, int i, abcs_image* h_out);
+
+/* Phase 1 and budget estimation (Alg 1 steps 2-3; Alg 2 steps 2-4).
+ * d_px:      uint8 pixels, px_bytes long; every image's cropped region must
+ *            lie inside it (checked against px_bytes).
+ * d_k:       out, int32[blocks]: DCT coefficients to sense from each block, the
+ *            length of its zigzag prefix.  BBV: m_i^2 of eq 22; DD: m^1 + m_i^2
+ *            (eq 23); ZZ: floor(B^2 C_R).
+ * d_offsets: out, int64[blocks]: block i's coefficients are
+ *            y[offsets[i] .. offsets[i] + k[i]) (exclusive prefix sum of k
+ *            within each image, plus the image's meas_offset).
+ * d_stat:    out, int32[blocks]: BBV_i (eq 19) or n_i (count of the first m^1
+ *            zigzag coefficients with |c| > T); 0 for ZZ.
+ * Budgets are exact integers: shares are floor(P w_i / S) of the pool P; a
+ * block whose share reaches its cap (B^2 - m^1) is fixed at the cap and the
+ * rest is re-split; the final leftover goes to the largest remainders
+ * (P w_i mod S), ties to the lower block index; all-zero weights split
+ * uniformly.  DD's |c| > T decisions are those of the float64 DCT computed in
+ * the fixed order T = X D^T then D T, sums ascending, no fused multiply-add. */
+int abcs_budget(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes,
+                int32_t* d_k, int64_t* d_offsets, int32_t* d_stat, void* stream);
+
+/* Phase 2 sensing (Alg 1 step 4; Alg 2 step 5): y[offsets[i] + z] =
+ * C_i[zigzag[z]] for z < k[i], where C_i = D X_i D^T is block i's orthonormal
+ * 2D DCT-II of the raw [0, 255] pixels (float32 arithmetic).
+ * d_y: out, float[meas]. */
+int abcs_sense(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes,
+               const int32_t* d_k, const int64_t* d_offsets, float* d_y, void* stream);
+
+/* Real-time decoder (Fig 1, I_o): zero-fill each block's unmeasured
+ * coefficients and apply the inverse 2D DCT X = D^T C D (float32).
+ * Needs only y, k and offsets (the side information), never pixels.
+ * d_out: out, float[pixels], each image H' x W' with row pitch W'. */
+int abcs_reconstruct(const abcs_plan* plan, const float* d_y, const int32_t* d_k,
+                     const int64_t* d_offsets, float* d_out, void* stream);
+
+/* Host copy of the float64 orthonormal DCT-II basis the library uses,
+ * D[u*B + j] = s_u cos((2j+1) u pi / (2B)), for checking.  B in {8, 16, 32}. */
+int abcs_dct_basis(int block, double* h_out);
+
+/* Message describing the last error returned on the calling thread. */
+const char* abcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABCS_H */

@@ -1,0 +1,10 @@
+"""MI355X-native adaptive block compressive sensing (AL-DCT-BBV / AL-DCT-DD,
+masked inverse 2D-DCT, IDA post-processing).
+
+Thin Python binding of the C ABI in include/abcs.h: it marshals torch device
+tensors to raw pointers and the current HIP stream; every step of the method
+runs in the gfx950 kernels of libabcs.so.  There is no CPU fallback: calls
+raise if the library is missing.
+"""
+from .api import (ZZ, BBV, DD, Plan, AbcsError, budget, sense, reconstruct,  # noqa: F401
+                  dct_basis, METHODS)

@@ -1,0 +1,67 @@
+"""ctypes loader and prototypes of libabcs.so (include/abcs.h)."""
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libabcs.so")
+
+ABCS_OK, ABCS_EINVAL, ABCS_EDOMAIN, ABCS_EUNSUPPORTED, ABCS_ENOSPACE, ABCS_EHIP = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EDOMAIN", -3: "EUNSUPPORTED", -4: "ENOSPACE", -5: "EHIP"}
+
+EXPORTS = [
+    "abcs_plan_create", "abcs_plan_destroy", "abcs_plan_totals", "abcs_plan_image",
+    "abcs_budget", "abcs_sense", "abcs_reconstruct", "abcs_dct_basis", "abcs_last_error",
+]
+
+
+class AbcsError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class ImageDesc(ctypes.Structure):
+    _fields_ = [
+        ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("row_pitch", ctypes.c_int32),
+        ("block", ctypes.c_int32), ("subrate", ctypes.c_double), ("method", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("pixel_offset", ctypes.c_int64),
+        ("block_offset", ctypes.c_int64), ("meas_offset", ctypes.c_int64),
+        ("out_offset", ctypes.c_int64), ("n_meas", ctypes.c_int64),
+        ("cropped_height", ctypes.c_int32), ("cropped_width", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2001_09632_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    L.abcs_plan_create.argtypes = [ctypes.POINTER(ImageDesc), i32, ctypes.POINTER(vp)]
+    L.abcs_plan_destroy.argtypes = [vp]
+    L.abcs_plan_destroy.restype = None
+    L.abcs_plan_totals.argtypes = [vp, P64, P64, P64]
+    L.abcs_plan_image.argtypes = [vp, i32, ctypes.POINTER(ImageDesc)]
+    L.abcs_budget.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    L.abcs_sense.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    L.abcs_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.abcs_dct_basis.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
+    L.abcs_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("abcs_plan_destroy", "abcs_last_error"):
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != ABCS_OK:
+        raise AbcsError(status, lib().abcs_last_error().decode(errors="replace"))

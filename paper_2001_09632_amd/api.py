@@ -1,0 +1,97 @@
+"""Python binding of libabcs (argument marshalling only)."""
+import ctypes
+
+from ._native import ImageDesc, AbcsError, check, lib  # noqa: F401
+
+ZZ, BBV, DD = 0, 1, 2
+METHODS = {"zz": ZZ, "bbv": BBV, "dd": DD}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Plan:
+    """A validated batch of images (abcs_plan_create).
+
+    images: iterable of dicts with keys height, width, block, subrate,
+    method (0/1/2 or 'zz'/'bbv'/'dd'), and optionally row_pitch (default
+    width rounded up to 4) and pixel_offset (default: images packed one after
+    the other).  Create it with the target device current.
+    """
+
+    def __init__(self, images):
+        imgs = list(images)
+        arr = (ImageDesc * max(1, len(imgs)))()
+        offset = 0
+        for i, d in enumerate(imgs):
+            m = d["method"]
+            m = METHODS[m] if isinstance(m, str) else int(m)
+            pitch = int(d.get("row_pitch", (int(d["width"]) + 3) // 4 * 4))
+            po = d.get("pixel_offset")
+            if po is None:
+                po = offset
+                offset += pitch * int(d["height"])
+                offset = (offset + 3) // 4 * 4
+            arr[i].height, arr[i].width, arr[i].row_pitch = int(d["height"]), int(d["width"]), pitch
+            arr[i].block, arr[i].subrate, arr[i].method = int(d["block"]), float(d["subrate"]), m
+            arr[i].reserved, arr[i].pixel_offset = int(d.get("reserved", 0)), int(po)
+        self._h = ctypes.c_void_p()
+        check(lib().abcs_plan_create(arr, len(imgs), ctypes.byref(self._h)))
+        self.n = len(imgs)
+        b, m, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(lib().abcs_plan_totals(self._h, ctypes.byref(b), ctypes.byref(m), ctypes.byref(p)))
+        self.blocks, self.meas, self.pixels = b.value, m.value, p.value
+        self.images = []
+        for i in range(self.n):
+            out = ImageDesc()
+            check(lib().abcs_plan_image(self._h, i, ctypes.byref(out)))
+            self.images.append({f: getattr(out, f) for f, _ in ImageDesc._fields_})
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().abcs_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def budget(plan, px, k, offsets, stat, stream=None):
+    """abcs_budget: px uint8 device tensor; k int32[blocks], offsets
+    int64[blocks], stat int32[blocks] device tensors (written)."""
+    check(lib().abcs_budget(plan.handle, _ptr(px), px.numel() * px.element_size(), _ptr(k),
+                            _ptr(offsets), _ptr(stat), _stream(stream)))
+
+
+def sense(plan, px, k, offsets, y, stream=None):
+    """abcs_sense: y float32[meas] device tensor (written)."""
+    check(lib().abcs_sense(plan.handle, _ptr(px), px.numel() * px.element_size(), _ptr(k),
+                           _ptr(offsets), _ptr(y), _stream(stream)))
+
+
+def reconstruct(plan, y, k, offsets, out, stream=None):
+    """abcs_reconstruct: out float32[pixels] device tensor (written)."""
+    check(lib().abcs_reconstruct(plan.handle, _ptr(y), _ptr(k), _ptr(offsets), _ptr(out),
+                                 _stream(stream)))
+
+
+def dct_basis(block):
+    """Host float64 DCT-II basis used by the library (B x B nested list)."""
+    buf = (ctypes.c_double * (block * block))()
+    check(lib().abcs_dct_basis(int(block), buf))
+    return [[buf[u * block + j] for j in range(block)] for u in range(block)]

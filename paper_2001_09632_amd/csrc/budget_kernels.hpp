@@ -1,0 +1,315 @@
+// Phase-1 statistics and per-image budget apportionment (Section V).
+#pragma once
+
+#include "common.hpp"
+#include "transform16.hpp"
+
+namespace abcs {
+
+// ---------------------------------------------------------------------------
+// BBV_i (eq 19): one thread per block.  With k_j = X0 + j L the block adds the
+// absolute differences of horizontally adjacent pixels (k_j - 1, k_j) along
+// its top row and of vertically adjacent pixels along its left column; the
+// bottom and right terms are the top row of the block below and the left
+// column of the block to the right, or the block's own last row / column at
+// the image edge.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kGroupThreads) void k_bbv_stats(const ImgDev* __restrict__ imgs,
+                                                            const Tile* __restrict__ tiles, int ntiles,
+                                                            const uint8_t* __restrict__ px,
+                                                            int32_t* __restrict__ stat) {
+  const int t = blockIdx.x * kGroupThreads + threadIdx.x;
+  const int ti = t / kTileBlocks, b = t % kTileBlocks;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  if (b >= tl.count) return;
+  const ImgDev im = imgs[tl.img];
+  const int blk = tl.first + b;
+  const int by = blk / im.nbx, bx = blk - by * im.nbx;
+  const uint8_t* base = px + im.px_off;
+  const int pitch = im.pitch, B = im.B;
+  const int r0 = by * B, c0 = bx * B;
+
+  auto row_var = [&](int r, int c) {
+    const uint8_t* p = base + (int64_t)r * pitch + c;
+    int s = 0;
+    for (int j = 0; j < im.nS; ++j) {
+      const int k = im.X0 + j * im.L;
+      s += abs((int)p[k] - (int)p[k - 1]);
+    }
+    return s;
+  };
+  auto col_var = [&](int c, int r) {
+    const uint8_t* p = base + (int64_t)r * pitch + c;
+    int s = 0;
+    for (int j = 0; j < im.nS; ++j) {
+      const int k = im.X0 + j * im.L;
+      s += abs((int)p[(int64_t)k * pitch] - (int)p[(int64_t)(k - 1) * pitch]);
+    }
+    return s;
+  };
+  const int top = row_var(r0, c0);
+  const int left = col_var(c0, r0);
+  const int bottom = (by + 1 < im.nby) ? row_var(r0 + B, c0) : row_var(r0 + B - 1, c0);
+  const int right = (bx + 1 < im.nbx) ? col_var(c0 + B, r0) : col_var(c0 + B - 1, r0);
+  stat[im.blk_off + blk] = top + left + bottom + right;
+}
+
+// ---------------------------------------------------------------------------
+// DD n_i: one wavefront per tile of 16x16 blocks.  The float32 MFMA transform
+// decides |c| > T for every coefficient further than kDDGuard from T; the rest
+// are recomputed in float64 in the fixed order of dct16_coef_f64.  kDDGuard is
+// well above the float32 error of the transform (pixels <= 255 give |error| <
+// 1e-2 for B = 16).
+// ---------------------------------------------------------------------------
+constexpr float kDDGuard = 0.0625f;
+
+__global__ __launch_bounds__(kGroupThreads) void k_dd_stats(const ImgDev* __restrict__ imgs,
+                                                           const Tile* __restrict__ tiles, int ntiles,
+                                                           const uint8_t* __restrict__ px,
+                                                           int32_t* __restrict__ stat) {
+  const int wave = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+  if (wave >= ntiles) return;
+  const Tile tl = tiles[wave];
+  const ImgDev im = imgs[tl.img];
+  Lane16 L;
+  lane16_init(L);
+  const int lane = threadIdx.x & 63;
+  const float T = (float)im.T;
+
+  uint32_t pw[kTileBlocks];
+#pragma unroll
+  for (int b = 0; b < kTileBlocks; ++b) {
+    if (b < tl.count) {
+      const int blk = tl.first + b;
+      const int by = blk / im.nbx, bx = blk - by * im.nbx;
+      const uint8_t* p = px + im.px_off + (int64_t)(by * 16 + L.n) * im.pitch + bx * 16 + 4 * L.g;
+      pw[b] = *(const uint32_t*)p;
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < kTileBlocks; ++b) {
+    if (b < tl.count) {
+      const int blk = tl.first + b;
+      float a[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[c] = (float)((pw[b] >> (8 * c)) & 0xffu);
+      const f32x4 C = dct16_fwd(a, L);
+      int cnt = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (L.zr[r] < im.m1) {
+          const float av = fabsf(C[r]);
+          if (av > T + kDDGuard) {
+            cnt += 1;
+          } else if (av >= T - kDDGuard) {
+            const int by = blk / im.nbx, bx = blk - by * im.nbx;
+            const uint8_t* bp = px + im.px_off + (int64_t)(by * 16) * im.pitch + bx * 16;
+            const double c64 = dct16_coef_f64(bp, im.pitch, 4 * L.g + r, L.n);
+            cnt += (fabs(c64) > (double)im.T) ? 1 : 0;
+          }
+        }
+      }
+      cnt = wave_sum_i32(cnt);
+      if (lane == 0) stat[im.blk_off + blk] = cnt;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Budget apportionment (eqs 22, 23 and the cap rule after eq 22), one
+// workgroup per image, exact integer arithmetic.
+//   1. a_i <- undecided for every block (the cap is > 0 for every rule).
+//   2. S = sum of undecided weights (all zero -> weight 1 each).
+//      q_i = floor(P w_i / S).  If some q_i >= cap: those blocks are fixed at
+//      the cap, P shrinks by what they took, repeat 2.
+//   3. Otherwise a_i = q_i plus one for the R = P - sum q_i blocks with the
+//      largest (P w_i mod S), ties to the lower index (radix select on the
+//      remainder, then a rank among equal remainders).
+//   4. DD adds the m^1 phase-1 coefficients; offsets = exclusive prefix sum.
+// Thread t owns the contiguous index range [t*per, t*per + per) so that index
+// order is thread order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum_t(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T>
+__device__ T group_sum(T v, T* sh) {
+  v = wave_sum_t(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < kWavesPerGroup; ++i) s += sh[i];
+  return s;
+}
+
+// Exclusive prefix sum over threads in thread order.
+template <typename T>
+__device__ T group_exclusive_scan(T v, T* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  T inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  __syncthreads();
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  T base = 0;
+  for (int i = 0; i < w; ++i) base += sh[i];
+  return base + inc - v;
+}
+
+__global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __restrict__ imgs,
+                                                            int32_t* __restrict__ stat_all,
+                                                            int32_t* __restrict__ k_all,
+                                                            int64_t* __restrict__ off_all) {
+  __shared__ int64_t sh64[kWavesPerGroup];
+  __shared__ int32_t hist[256];
+  __shared__ int64_t sel_sh[2];
+  const ImgDev im = imgs[blockIdx.x];
+  const int nB = im.nB;
+  int32_t* w = stat_all + im.blk_off;
+  int32_t* k = k_all + im.blk_off;
+  int64_t* off = off_all + im.blk_off;
+  const int tid = threadIdx.x;
+  const int per = (nB + kGroupThreads - 1) / kGroupThreads;
+  const int i0 = min(nB, tid * per), i1 = min(nB, i0 + per);
+
+  if (im.mode == kModeZZ) {
+    for (int i = i0; i < i1; ++i) {
+      k[i] = im.kz;
+      w[i] = 0;
+      off[i] = im.meas_off + (int64_t)i * im.kz;
+    }
+    return;
+  }
+
+  const int64_t cap = im.cap;
+  int64_t P = im.pool;
+  for (int i = i0; i < i1; ++i) k[i] = -1;  // undecided
+
+  int64_t S = 0;
+  bool uniform = false;
+  for (;;) {
+    int64_t sw = 0, na = 0;
+    for (int i = i0; i < i1; ++i)
+      if (k[i] < 0) { sw += w[i]; na += 1; }
+    S = group_sum(sw, sh64);
+    const int64_t A = group_sum(na, sh64);
+    if (A == 0) break;
+    uniform = (S == 0);
+    if (uniform) S = A;
+    int64_t used = 0, nover = 0;
+    for (int i = i0; i < i1; ++i) {
+      if (k[i] < 0) {
+        const int64_t wi = uniform ? 1 : (int64_t)w[i];
+        if ((P * wi) / S >= cap) nover += 1;
+      }
+    }
+    nover = group_sum(nover, sh64);
+    if (nover == 0) break;
+    for (int i = i0; i < i1; ++i) {
+      if (k[i] < 0) {
+        const int64_t wi = uniform ? 1 : (int64_t)w[i];
+        if ((P * wi) / S >= cap) { k[i] = (int32_t)cap; used += cap; }
+      }
+    }
+    P -= group_sum(used, sh64);
+  }
+
+  // Floors of the final split and the leftover R.
+  int64_t sq = 0;
+  for (int i = i0; i < i1; ++i) {
+    if (k[i] < 0) {
+      const int64_t wi = uniform ? 1 : (int64_t)w[i];
+      sq += (P * wi) / S;
+    }
+  }
+  const int64_t R = P - group_sum(sq, sh64);
+
+  // Radix select of the R-th largest remainder tau (8-bit digits, MSB first).
+  int64_t tau = 0, need = R;
+  if (R > 0 && S > 1) {
+    const int bits = 64 - __clzll((unsigned long long)(S - 1));
+    for (int shift = ((bits + 7) / 8) * 8 - 8; shift >= 0; shift -= 8) {
+      hist[tid] = 0;  // kGroupThreads == 256 bins
+      __syncthreads();
+      const uint64_t hi_mask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
+      for (int i = i0; i < i1; ++i) {
+        if (k[i] < 0) {
+          const int64_t wi = uniform ? 1 : (int64_t)w[i];
+          const int64_t pw = P * wi;
+          const uint64_t rem = (uint64_t)(pw - (pw / S) * S);
+          if ((rem & hi_mask) == ((uint64_t)tau & hi_mask)) atomicAdd(&hist[(rem >> shift) & 255u], 1);
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int64_t cum = 0;
+        int d = 255;
+        for (; d > 0; --d) {
+          if (cum + hist[d] >= need) break;
+          cum += hist[d];
+        }
+        sel_sh[0] = d;
+        sel_sh[1] = need - cum;
+      }
+      __syncthreads();
+      tau |= (int64_t)sel_sh[0] << shift;
+      need = sel_sh[1];
+      __syncthreads();
+    }
+  }
+
+  // Final values: floor + 1 for remainders above tau and for the first `need`
+  // (by index) remainders equal to tau.
+  int64_t neq = 0;
+  if (R > 0) {
+    for (int i = i0; i < i1; ++i) {
+      if (k[i] < 0) {
+        const int64_t wi = uniform ? 1 : (int64_t)w[i];
+        const int64_t pw = P * wi;
+        if (pw - (pw / S) * S == tau) neq += 1;
+      }
+    }
+  }
+  int64_t rank = group_exclusive_scan(neq, sh64);
+  const int32_t add = (im.mode == kModeDD) ? im.m1 : 0;
+  int64_t ksum = 0;
+  for (int i = i0; i < i1; ++i) {
+    int64_t ki = k[i];
+    if (ki < 0) {
+      const int64_t wi = uniform ? 1 : (int64_t)w[i];
+      const int64_t pw = P * wi;
+      const int64_t q = pw / S, rem = pw - q * S;
+      ki = q;
+      if (R > 0) {
+        if (rem > tau) {
+          ki += 1;
+        } else if (rem == tau) {
+          if (rank < need) ki += 1;
+          rank += 1;
+        }
+      }
+    }
+    ki += add;
+    k[i] = (int32_t)ki;
+    ksum += ki;
+  }
+  int64_t base = group_exclusive_scan(ksum, sh64) + im.meas_off;
+  for (int i = i0; i < i1; ++i) {
+    off[i] = base;
+    base += k[i];
+  }
+}
+
+}  // namespace abcs

@@ -1,0 +1,46 @@
+// Internal definitions shared by the host side and the kernels of libabcs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace abcs {
+
+// Blocks handled by one wavefront in the block-parallel kernels.  Tiles never
+// cross an image boundary, so a wave reads one image descriptor per tile.
+constexpr int kTileBlocks = 16;
+constexpr int kWavesPerGroup = 4;
+constexpr int kGroupThreads = 64 * kWavesPerGroup;
+
+enum Mode : int32_t { kModeZZ = 0, kModeBBV = 1, kModeDD = 2 };
+
+// Per-image parameters, derived on the host from the descriptor (eqs 16-21,
+// Table 1, Alg 2 step 2) and read by every kernel.
+struct ImgDev {
+  int64_t px_off;    // byte offset of pixel (0,0)
+  int64_t blk_off;   // first block in batch arrays
+  int64_t meas_off;  // first coefficient in y
+  int64_t out_off;   // first decoded pixel
+  int64_t pool;      // P: coefficients apportioned by weight
+  int64_t n_meas;    // coefficients of this image in y
+  int32_t pitch;     // bytes per pixel row
+  int32_t Hc, Wc;    // cropped size
+  int32_t nbx, nby, nB;
+  int32_t B;
+  int32_t mode;      // effective budget rule (BBV with n_S = 0 runs as ZZ)
+  int32_t kz;        // floor(B^2 C_R)
+  int32_t L, X0, nS; // BBV sampling stride, first offset, samples per side
+  int32_t m1;        // DD phase-1 coefficients
+  int32_t T;         // DD threshold
+  int32_t cap;       // per-block cap of the apportioned part
+  int32_t pad_;
+};
+
+struct Tile {
+  int32_t img;    // image index
+  int32_t first;  // first block (index inside the image)
+  int32_t count;  // blocks in this tile (1..kTileBlocks)
+  int32_t pad_;
+};
+
+}  // namespace abcs

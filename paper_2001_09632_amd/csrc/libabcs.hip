@@ -1,0 +1,8 @@
+// libabcs: MI355X (gfx950) adaptive block compressive sensing.
+// Single translation unit: kernels, their __constant__ tables and the host ABI.
+#include "../../include/abcs.h"
+#include "common.hpp"
+#include "transform16.hpp"
+#include "budget_kernels.hpp"
+#include "sense_kernels.hpp"
+#include "api.cpp.inc"

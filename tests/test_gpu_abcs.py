@@ -1,0 +1,137 @@
+"""GPU parity of budget / sense / reconstruct against the FP64 oracle.
+
+Bars: per-block budgets k, statistics (BBV_i, n_i) and offsets bit-exact;
+measurements y within 1e-2 absolute (float32 transform of [0, 255] pixels:
+with B = 16 every coefficient is a sum of 256 products whose magnitudes add
+up to at most 255 * 4 * 4, and two 16-term float32 accumulations keep the
+error below (2*16 + 2) * 2^-24 * 4080 < 1e-2); decoded pixels within 1e-3
+absolute of the oracle's decoding of the same measurements.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import abcs as orc
+
+from gpu_util import Run, pack_images
+
+pytestmark = pytest.mark.gpu
+
+Y_TOL = 1e-2
+PX_TOL = 1e-3
+
+
+def _check_image(run, i, img, block, cr, method, check_y=True, check_px=True):
+    got = run.image(i)
+    k, stat = orc.budget(img, block, cr, method)
+    assert np.array_equal(got["k"], k), f"k mismatch (image {i}, method {method}, C_R {cr})"
+    assert np.array_equal(got["stat"], stat), f"stat mismatch (image {i})"
+    assert np.array_equal(got["off"], orc.offsets(k)), f"offset mismatch (image {i})"
+    assert got["y"].size == k.sum()
+    if check_y:
+        y = orc.sense(img, block, k)
+        err = np.max(np.abs(got["y"] - y)) if y.size else 0.0
+        assert err < Y_TOL, f"y error {err} (image {i})"
+    if check_px:
+        H, W = img.shape
+        rec = orc.reconstruct(got["y"].astype(np.float64), block, k, H, W)
+        err = np.max(np.abs(got["out"] - rec))
+        assert err < PX_TOL, f"pixel error {err} (image {i})"
+
+
+def test_single_image_bbv_256():
+    img = synth.synth_image(0, 256, 256)
+    px, d = pack_images([img])
+    run = Run(px, [dict(d[0], block=16, subrate=0.25, method="bbv")]).budget().sense().reconstruct().fetch()
+    _check_image(run, 0, img, 16, 0.25, orc.BBV)
+
+
+def test_methods_subrates_ragged_sizes():
+    imgs = [synth.synth_image(s, h, w) for s, (h, w) in enumerate([(256, 200), (64, 48), (170, 181), (16, 16)])]
+    px, d = pack_images(imgs, pitch_pad=8)
+    entries, cases = [], []
+    for i, img in enumerate(imgs):
+        for m in ("zz", "bbv", "dd"):
+            for cr in (0.02, 0.1, 0.3, 0.5, 1.0):
+                if m == "bbv" and cr > 0.5:
+                    continue
+                if img.shape == (16, 16) and m == "bbv" and cr < 0.1:
+                    continue
+                entries.append(dict(d[i], block=16, subrate=cr, method=m))
+                cases.append((i, cr, orc.METHOD_NAMES[m]))
+    run = Run(px, entries).budget().sense().reconstruct().fetch()
+    for j, (i, cr, m) in enumerate(cases):
+        _check_image(run, j, imgs[i], 16, cr, m)
+
+
+def test_exact_recovery_full_subrate():
+    img = synth.synth_image(77, 128, 96)
+    px, d = pack_images([img])
+    run = Run(px, [dict(d[0], block=16, subrate=1.0, method=m) for m in ("zz", "dd")]).budget().sense() \
+        .reconstruct().fetch()
+    for j in range(2):
+        got = run.image(j)
+        assert np.all(got["k"] == 256)
+        assert np.max(np.abs(got["out"] - img)) < PX_TOL
+
+
+def test_degenerate_images():
+    flat = np.full((64, 64), 128, np.uint8)                  # all weights 0 -> uniform split
+    black = np.zeros((64, 64), np.uint8)
+    one = np.full((64, 64), 90, np.uint8)
+    one[16:32, 16:32] = synth.synth_image(3, 16, 16)          # one textured block: cap overflow
+    one[16:32, 16:32:2] = 255
+    checker = ((np.indices((48, 48)).sum(axis=0) % 2) * 255).astype(np.uint8)   # saturated texture
+    dc_tie = np.zeros((32, 32), np.uint8)
+    dc_tie[:15, :16] = 4                                      # block sum 960: DC == T = 60 exactly
+    dc_tie[:, 16:] = 4
+    imgs = [flat, black, one, checker, dc_tie]
+    px, d = pack_images(imgs)
+    entries, cases = [], []
+    for i in range(len(imgs)):
+        for m in ("bbv", "dd", "zz"):
+            for cr in (0.1, 0.25, 0.5):
+                entries.append(dict(d[i], block=16, subrate=cr, method=m))
+                cases.append((i, cr, orc.METHOD_NAMES[m]))
+    run = Run(px, entries).budget().sense().reconstruct().fetch()
+    for j, (i, cr, m) in enumerate(cases):
+        _check_image(run, j, imgs[i], 16, cr, m)
+
+
+def test_decoder_on_oracle_measurements():
+    img = synth.synth_image(5, 256, 256)
+    px, d = pack_images([img])
+    run = Run(px, [dict(d[0], block=16, subrate=0.2, method="dd")]).budget().fetch()
+    k, _, y = orc.encode(img, 16, 0.2, orc.DD)
+    import torch
+    run.reconstruct(torch.from_numpy(y.astype(np.float32)).to(run.y.device)).fetch()
+    rec = orc.reconstruct(y.astype(np.float32).astype(np.float64), 16, k, 256, 256)
+    assert np.max(np.abs(run.image(0)["out"] - rec)) < PX_TOL
+
+
+def test_runs_are_bitwise_repeatable():
+    imgs = [synth.synth_image(s, 128, 128) for s in range(3)]
+    px, d = pack_images(imgs)
+    entries = [dict(d[i], block=16, subrate=0.3, method=m) for i in range(3) for m in ("bbv", "dd")]
+    a = Run(px, entries).budget().sense().reconstruct().fetch()
+    b = Run(px, entries).budget().sense().reconstruct().fetch()
+    assert np.array_equal(a.h_k, b.h_k) and np.array_equal(a.h_y, b.h_y) and np.array_equal(a.h_out, b.h_out)
+
+
+def test_batch_64x512_all_estimators_and_subrates():
+    """The 64 x 512^2 batch with BBV and DD at C_R 0.1..0.5 in one plan, run
+    exactly as the benchmark launches it: every budget, statistic and offset
+    bit-exact; y and pixels compared in full on 8 images per combination."""
+    seeds = list(range(1000, 1064))
+    imgs = [synth.synth_image(s, 512, 512) for s in seeds]
+    px, d = pack_images(imgs)
+    entries, cases = [], []
+    for m in ("bbv", "dd"):
+        for cr in (0.1, 0.2, 0.3, 0.4, 0.5):
+            for i in range(64):
+                entries.append(dict(d[i], block=16, subrate=cr, method=m))
+                cases.append((i, cr, orc.METHOD_NAMES[m]))
+    run = Run(px, entries).budget().sense().reconstruct().fetch()
+    for j, (i, cr, m) in enumerate(cases):
+        full = (i % 8 == 0)
+        _check_image(run, j, imgs[i], 16, cr, m, check_y=full, check_px=full)
