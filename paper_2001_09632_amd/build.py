@@ -22,7 +22,8 @@ def sources():
 
 def build(verbose=False):
     """Compile libabcs.so; raises CalledProcessError on failure."""
-    cmd = [HIPCC] + FLAGS + ["-o", LIB + ".tmp", os.path.join(CSRC, "libabcs.hip")]
+    inc = os.path.join(os.path.dirname(PKG), "include")
+    cmd = [HIPCC] + FLAGS + ["-I", inc, "-o", LIB + ".tmp", os.path.join(CSRC, "libabcs.hip")]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)

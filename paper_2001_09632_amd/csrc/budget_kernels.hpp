@@ -58,9 +58,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_bbv_stats(const ImgDev* __res
 // ---------------------------------------------------------------------------
 // DD n_i: one wavefront per tile of 16x16 blocks.  The float32 MFMA transform
 // decides |c| > T for every coefficient further than kDDGuard from T; the rest
-// are recomputed in float64 in the fixed order of dct16_coef_f64.  kDDGuard is
-// well above the float32 error of the transform (pixels <= 255 give |error| <
-// 1e-2 for B = 16).
+// are recomputed in float64 in the fixed order of dct16_coef_f64 from the
+// block staged in LDS.  kDDGuard is well above the float32 error of the
+// transform (pixels <= 255 give |error| < 1e-2 for B = 16).
 // ---------------------------------------------------------------------------
 constexpr float kDDGuard = 0.0625f;
 
@@ -68,52 +68,60 @@ __global__ __launch_bounds__(kGroupThreads) void k_dd_stats(const ImgDev* __rest
                                                            const Tile* __restrict__ tiles, int ntiles,
                                                            const uint8_t* __restrict__ px,
                                                            int32_t* __restrict__ stat) {
-  const int wave = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+  __shared__ double sD[256];
+  __shared__ uint32_t sblk[kWavesPerGroup][64];
+  sD[threadIdx.x] = c_D16d[threadIdx.x];
+  __syncthreads();
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
   const Tile tl = tiles[wave];
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane16_init(L);
   const int lane = threadIdx.x & 63;
+  uint32_t* words = sblk[wave_in_group()];
   const float T = (float)im.T;
 
   uint32_t pw[kTileBlocks];
 #pragma unroll
   for (int b = 0; b < kTileBlocks; ++b) {
-    if (b < tl.count) {
-      const int blk = tl.first + b;
-      const int by = blk / im.nbx, bx = blk - by * im.nbx;
-      const uint8_t* p = px + im.px_off + (int64_t)(by * 16 + L.n) * im.pitch + bx * 16 + 4 * L.g;
-      pw[b] = *(const uint32_t*)p;
-    }
+    const bool valid = b < tl.count;
+    pw[b] = load_block_px(im, px, tl.first + (valid ? b : 0), valid, L);
   }
+  int32_t my_stat = 0;  // lane b keeps block b's count
 #pragma unroll
   for (int b = 0; b < kTileBlocks; ++b) {
-    if (b < tl.count) {
-      const int blk = tl.first + b;
+    {
       float a[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) a[c] = (float)((pw[b] >> (8 * c)) & 0xffu);
       const f32x4 C = dct16_fwd(a, L);
-      int cnt = 0;
+      bool above[4], unsure[4];
+      bool any_unsure = false;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (L.zr[r] < im.m1) {
-          const float av = fabsf(C[r]);
-          if (av > T + kDDGuard) {
-            cnt += 1;
-          } else if (av >= T - kDDGuard) {
-            const int by = blk / im.nbx, bx = blk - by * im.nbx;
-            const uint8_t* bp = px + im.px_off + (int64_t)(by * 16) * im.pitch + bx * 16;
-            const double c64 = dct16_coef_f64(bp, im.pitch, 4 * L.g + r, L.n);
-            cnt += (fabs(c64) > (double)im.T) ? 1 : 0;
-          }
-        }
+        const float av = fabsf(C[r]);
+        const bool in = L.zr[r] < im.m1;
+        above[r] = in && (av > T + kDDGuard);
+        unsure[r] = in && !above[r] && (av >= T - kDDGuard);
+        any_unsure |= unsure[r];
       }
-      cnt = wave_sum_i32(cnt);
-      if (lane == 0) stat[im.blk_off + blk] = cnt;
+      if (__ballot(any_unsure) != 0) {
+        words[lane] = pw[b];
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (unsure[r]) above[r] = fabs(dct16_coef_f64(words, sD, 4 * L.g + r, L.n)) > (double)im.T;
+        }
+        wave_lds_sync();
+      }
+      int cnt = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cnt += __popcll(__ballot(above[r]));
+      if (lane == b) my_stat = cnt;
     }
   }
+  if (lane < tl.count) stat[im.blk_off + tl.first + lane] = my_stat;
 }
 
 // ---------------------------------------------------------------------------
@@ -253,15 +261,17 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
         }
       }
       __syncthreads();
+      // Bin counts summed from the top digit down: the selected digit d is
+      // the one where the count of larger-or-equal remainders reaches `need`.
       if (tid == 0) {
-        int64_t cum = 0;
-        int d = 255;
-        for (; d > 0; --d) {
-          if (cum + hist[d] >= need) break;
-          cum += hist[d];
-        }
-        sel_sh[0] = d;
-        sel_sh[1] = need - cum;
+        sel_sh[0] = 0;
+        sel_sh[1] = need;
+      }
+      const int32_t bin = hist[255 - tid];
+      const int64_t above_incl = group_exclusive_scan((int64_t)bin, sh64) + bin;
+      if (above_incl >= need && above_incl - bin < need) {
+        sel_sh[0] = 255 - tid;
+        sel_sh[1] = need - (above_incl - bin);
       }
       __syncthreads();
       tau |= (int64_t)sel_sh[0] << shift;

@@ -43,4 +43,15 @@ struct Tile {
   int32_t pad_;
 };
 
+// Index of the calling wavefront inside its workgroup, as a scalar (the
+// compiler cannot prove threadIdx.x >> 6 uniform on its own, and everything
+// derived from it would otherwise live in vector registers).
+__device__ __forceinline__ int wave_in_group() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Raw buffer resource over `bytes` bytes at `base`: loads beyond the range
+// return 0 and stores beyond it are dropped by the hardware range check.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+
 }  // namespace abcs

@@ -1,6 +1,6 @@
 // libabcs: MI355X (gfx950) adaptive block compressive sensing.
 // Single translation unit: kernels, their __constant__ tables and the host ABI.
-#include "../../include/abcs.h"
+#include "abcs.h"
 #include "common.hpp"
 #include "transform16.hpp"
 #include "budget_kernels.hpp"

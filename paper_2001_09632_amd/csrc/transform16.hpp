@@ -21,6 +21,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "common.hpp"
+
 namespace abcs {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -70,6 +72,17 @@ __device__ __forceinline__ f32x4 idct16_inv(const float e[4], const Lane16& L) {
   return out;
 }
 
+// Pixel operand of a lane for block `blk` of an image: row n, columns
+// 4g .. 4g+3, read through a resource spanning the block's 16 rows (an empty
+// resource, for a slot past the end of a tile, reads 0).
+__device__ __forceinline__ uint32_t load_block_px(const ImgDev& im, const uint8_t* px, int blk, bool valid,
+                                                  const Lane16& L) {
+  const int by = blk / im.nbx, bx = blk - by * im.nbx;
+  const uint8_t* base = px + im.px_off + (int64_t)(by * 16) * im.pitch + bx * 16;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, valid ? 15 * im.pitch + 16 : 0);
+  return __builtin_amdgcn_raw_buffer_load_b32(rs, L.n * im.pitch + 4 * L.g, 0, 0);
+}
+
 // Order the wave's LDS writes before its following LDS reads (and reads before
 // later writes).  LDS instructions of one wavefront execute in issue order;
 // this stops the compiler from moving accesses across the point.
@@ -94,17 +107,21 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
 // Float64 DCT coefficient (u, v) of a 16x16 uint8 block in the fixed order
 // T[r] = sum_j X[r][j] D[v][j] (j ascending), C = sum_r D[u][r] T[r]
 // (r ascending), every product and sum rounded on its own.  Used to settle
-// DD threshold decisions that the float32 path cannot decide.
-__device__ __attribute__((noinline)) double dct16_coef_f64(const uint8_t* blk, int pitch, int u, int v) {
+// DD threshold decisions that the float32 path cannot decide.  `words` is the
+// block staged in LDS in the transform's operand layout: word 16g + r holds
+// pixels (r, 4g .. 4g+3), one per byte; `D` is the float64 basis.
+__device__ __attribute__((noinline)) double dct16_coef_f64(const uint32_t* words, const double* D, int u, int v) {
 #pragma clang fp contract(off)
   double c = 0.0;
   for (int r = 0; r < 16; ++r) {
     double t = 0.0;
+#pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const double p = (double)blk[r * pitch + j] * c_D16d[v * 16 + j];
+      const double x = (double)((words[(j >> 2) * 16 + r] >> (8 * (j & 3))) & 0xffu);
+      const double p = x * D[v * 16 + j];
       t = t + p;
     }
-    const double q = c_D16d[u * 16 + r] * t;
+    const double q = D[u * 16 + r] * t;
     c = c + q;
   }
   return c;
