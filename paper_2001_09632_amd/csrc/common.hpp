@@ -36,11 +36,16 @@ struct ImgDev {
   int32_t pad_;
 };
 
+// Up to kTileBlocks horizontally adjacent blocks of one block row of one
+// image.  Offsets of the tile's first block are precomputed so that a block's
+// addresses are the tile's plus a compile-time multiple of 16.
 struct Tile {
-  int32_t img;    // image index
-  int32_t first;  // first block (index inside the image)
-  int32_t count;  // blocks in this tile (1..kTileBlocks)
-  int32_t pad_;
+  int32_t img;     // image index
+  int32_t first;   // first block (raster index inside the image)
+  int32_t count;   // blocks in this tile (1..kTileBlocks)
+  int32_t by;      // block row
+  int64_t px_base; // byte offset of the first block's top-left pixel
+  int64_t out_base;// float offset of the first block's top-left decoded pixel
 };
 
 // Index of the calling wavefront inside its workgroup, as a scalar (the

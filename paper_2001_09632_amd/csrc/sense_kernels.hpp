@@ -17,59 +17,68 @@ __device__ __forceinline__ int guard_count(const ImgDev& im, int kk, int64_t off
   return c < 256 ? (int)c : 256;
 }
 
-// y[off_i + z] = C_i[zigzag[z]] for z < k_i.  Each lane stores its four
-// coefficients at their zigzag rank through a buffer resource that spans
-// exactly the block's k_i entries of y, so coefficients beyond the budget are
-// dropped by the range check.  The tile loop is straight-line code: slots past
-// the end of a tile get empty resources.
+// Per-wave LDS staging of one block's coefficients in zigzag order.
+struct WaveLds {
+  float c[256];
+};
+
+// y[off_i + z] = C_i[zigzag[z]] for z < k_i.  The transform output goes to
+// LDS at its zigzag rank and leaves with unit-stride stores of the block's k_i
+// coefficients (slot z of store q is lane + 64 q); slots at or beyond k_i get
+// an out-of-range offset and are dropped.
 __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restrict__ imgs,
                                                           const Tile* __restrict__ tiles, int ntiles,
                                                           const uint8_t* __restrict__ px,
                                                           const int32_t* __restrict__ k_all,
                                                           const int64_t* __restrict__ off_all,
                                                           float* __restrict__ y) {
+  __shared__ WaveLds lds[kWavesPerGroup];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
   const Tile tl = tiles[wave];
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane16_init(L);
-  int zoff[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) zoff[r] = 4 * L.zr[r];
-
+  TileIO io;
+  tile_io_init(io, im, tl, px, y, k_all, off_all, L);
+  float* buf = lds[wave_in_group()].c;
+  const int lane = threadIdx.x & 63;
   uint32_t pw[kTileBlocks];
 #pragma unroll
-  for (int b = 0; b < kTileBlocks; ++b) {
-    const bool valid = b < tl.count;
-    pw[b] = load_block_px(im, px, tl.first + (valid ? b : 0), valid, L);
-  }
-  const int32_t* kt = k_all + im.blk_off + tl.first;
-  const int64_t* ot = off_all + im.blk_off + tl.first;
+  for (int b = 0; b < kTileBlocks; ++b) pw[b] = tile_px(io, b);
 #pragma unroll
   for (int b = 0; b < kTileBlocks; ++b) {
-    const bool valid = b < tl.count;
-    const int bi = valid ? b : 0;
-    const int64_t off = ot[bi];
-    const int kk = valid ? guard_count(im, kt[bi], off) : 0;
     float a[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) a[c] = (float)((pw[b] >> (8 * c)) & 0xffu);
     const f32x4 C = dct16_fwd(a, L);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(y + off, 4 * kk);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(C[r]), rs, zoff[r], 0, 0);
+    for (int r = 0; r < 4; ++r) buf[L.zr[r]] = C[r];
+    wave_lds_sync();
+    const int kk = __builtin_amdgcn_readlane(io.k, b);
+    const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(io.rel_lo, b);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (64 * q < kk) {
+        const int z = lane + 64 * q;
+        const uint32_t voff = z < kk ? rel4 + 4u * (uint32_t)z : 0xffffffffu;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(buf[z]), io.y, voff, 0, 0);
+      }
+    }
+    wave_lds_sync();
   }
 }
 
 // out = D^T C D per block with C zero beyond the block's k_i zigzag entries.
-// Each lane gathers the four coefficients it feeds to the transform straight
-// from y through a buffer resource spanning the block's k_i entries; ranks
-// beyond k_i read as 0, which is the zero fill.  Gathers for block b + kAhead
-// are issued while block b is transformed.  Straight-line code: slots past the
-// end of a tile get empty resources.
-constexpr int kAhead = 4;
+// A block's k_i coefficients arrive with unit-stride loads (slots past k_i get
+// out-of-range offsets and read 0, the zero fill), go to LDS in zigzag order
+// and are gathered from there in the transform's operand layout.  All loads of
+// a tile are issued before any store.  Blocks are stored in pairs: lanes n < 8
+// of each 16-lane row hold rows of block b and lanes n >= 8 rows of block b + 1
+// (a DPP row rotation), so every store writes 8 rows x 128 bytes.
+__device__ __forceinline__ float row_ror8(float v) {
+  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), 0x128, 0xf, 0xf, false));
+}
 
 __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* __restrict__ imgs,
                                                                 const Tile* __restrict__ tiles, int ntiles,
@@ -77,43 +86,68 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
                                                                 const int32_t* __restrict__ k_all,
                                                                 const int64_t* __restrict__ off_all,
                                                                 float* __restrict__ out) {
+  __shared__ WaveLds lds[kWavesPerGroup][2];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
   const Tile tl = tiles[wave];
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane16_init(L);
-  int zoff[4];
+  TileIO io;
+  tile_io_init(io, im, tl, nullptr, y, k_all, off_all, L);
+  const int lane = threadIdx.x & 63;
+  float v[kTileBlocks][4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) zoff[c] = 4 * L.zr[c];
-  const int32_t* kt = k_all + im.blk_off + tl.first;
-  const int64_t* ot = off_all + im.blk_off + tl.first;
-  const int out_lane = (L.n * im.Wc + 4 * L.g) * 4;   // byte offset of the lane's row segment
-
-  float e[kTileBlocks][4];
+  for (int b = 0; b < kTileBlocks; ++b) {
+    const int kk = __builtin_amdgcn_readlane(io.k, b);
+    const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(io.rel_lo, b);
 #pragma unroll
-  for (int s = 0; s < kTileBlocks + kAhead; ++s) {
-    if (s < kTileBlocks) {
-      const bool valid = s < tl.count;
-      const int si = valid ? s : 0;
-      const int64_t off = ot[si];
-      const int kk = valid ? guard_count(im, kt[si], off) : 0;
-      const __amdgpu_buffer_rsrc_t rs = make_rsrc(y + off, 4 * kk);
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        e[s][c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, zoff[c], 0, 0));
+    for (int q = 0; q < 4; ++q) {
+      const int z = lane + 64 * q;
+      const uint32_t voff = z < kk ? rel4 + 4u * (uint32_t)z : 0xffffffffu;
+      v[b][q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(io.y, voff, 0, 0));
     }
-    const int b = s - kAhead;
-    if (b >= 0) {
-      const bool valid = b < tl.count;
-      const f32x4 X = idct16_inv(e[b], L);
-      const int blk = tl.first + (valid ? b : 0);
-      const int by = blk / im.nbx, bx = blk - by * im.nbx;
-      const __amdgpu_buffer_rsrc_t ro =
-          make_rsrc(out + im.out_off + (int64_t)(by * 16) * im.Wc + bx * 16, valid ? 4 * (15 * im.Wc + 16) : 0);
-      __builtin_amdgcn_raw_buffer_store_b128(
-          __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned int, X), ro, out_lane, 0, 0);
+  }
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + tl.out_base, 4 * (15 * im.Wc + 16 * tl.count));
+  const bool lo = L.n < 8;
+  const int row = lo ? L.n : L.n - 8;
+  const uint32_t o1 = 4u * (uint32_t)(row * im.Wc + (lo ? 0 : 16) + 4 * L.g);
+  const uint32_t o2 = o1 + 4u * 8u * (uint32_t)im.Wc;
+  float* buf0 = lds[wave_in_group()][0].c;
+  float* buf1 = lds[wave_in_group()][1].c;
+#pragma unroll
+  for (int b = 0; b < kTileBlocks; b += 2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      buf0[lane + 64 * q] = v[b][q];
+      buf1[lane + 64 * q] = v[b + 1][q];
     }
+    wave_lds_sync();
+    float e0[4], e1[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      e0[c] = buf0[L.zr[c]];
+      e1[c] = buf1[L.zr[c]];
+    }
+    wave_lds_sync();
+    const f32x4 A = idct16_inv(e0, L);
+    const f32x4 Bv = idct16_inv(e1, L);
+    f32x4 S1, S2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float ra = row_ror8(A[r]);
+      const float rb = row_ror8(Bv[r]);
+      S1[r] = lo ? A[r] : rb;
+      S2[r] = lo ? ra : Bv[r];
+    }
+    // Slots past the tile's end get out-of-range offsets (the resource's
+    // linear extent alone would let them reach the next pixel row).
+    const bool keep = lo ? (b < tl.count) : (b + 1 < tl.count);
+    const uint32_t v1 = keep ? o1 + 64u * b : 0xffffffffu;
+    const uint32_t v2 = keep ? o2 + 64u * b : 0xffffffffu;
+    typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, S1), ro, v1, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, S2), ro, v2, 0, 0);
   }
 }
 

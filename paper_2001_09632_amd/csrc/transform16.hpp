@@ -72,15 +72,44 @@ __device__ __forceinline__ f32x4 idct16_inv(const float e[4], const Lane16& L) {
   return out;
 }
 
-// Pixel operand of a lane for block `blk` of an image: row n, columns
-// 4g .. 4g+3, read through a resource spanning the block's 16 rows (an empty
-// resource, for a slot past the end of a tile, reads 0).
-__device__ __forceinline__ uint32_t load_block_px(const ImgDev& im, const uint8_t* px, int blk, bool valid,
-                                                  const Lane16& L) {
-  const int by = blk / im.nbx, bx = blk - by * im.nbx;
-  const uint8_t* base = px + im.px_off + (int64_t)(by * 16) * im.pitch + bx * 16;
-  const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, valid ? 15 * im.pitch + 16 : 0);
-  return __builtin_amdgcn_raw_buffer_load_b32(rs, L.n * im.pitch + 4 * L.g, 0, 0);
+// Per-tile addressing of the 16x16-block kernels.  Every block of a tile
+// reads and writes through resources set up once per tile; a block's own
+// addresses differ from the tile's by compile-time multiples of 16 pixels, and
+// the hardware range check of each resource keeps every access inside the
+// tile's pixels, the image's part of y and the tile's output rows.
+struct TileIO {
+  __amdgpu_buffer_rsrc_t px;   // uint8 pixels of the tile's 16 rows
+  int px_lane;                 // byte offset of the lane's 4 pixels in block 0
+  __amdgpu_buffer_rsrc_t y;    // the image's coefficients in y
+  int32_t k;                   // lane b < count: k of block b
+  int32_t rel_lo;              // lane b < count: offsets[b] - meas_off (low 32 bits)
+};
+
+__device__ __forceinline__ void tile_io_init(TileIO& io, const ImgDev& im, const Tile& tl, const uint8_t* px,
+                                             const float* y, const int32_t* k_all, const int64_t* off_all,
+                                             const Lane16& L) {
+  io.px = make_rsrc(px + tl.px_base, px ? 15 * im.pitch + 16 * tl.count : 0);
+  io.px_lane = L.n * im.pitch + 4 * L.g;
+  io.y = make_rsrc(y + im.meas_off, y ? (int)(4 * im.n_meas) : 0);
+  const int lane = threadIdx.x & 63;
+  const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(off_all + im.blk_off + tl.first, 8 * tl.count);
+  io.k = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rk, 4 * lane, 0, 0);
+  io.rel_lo = (int32_t)(__builtin_amdgcn_raw_buffer_load_b32(ro, 8 * lane, 0, 0) - (uint32_t)im.meas_off);
+}
+
+// Lane's pixel word of block b of the tile (0 past the tile's end).
+__device__ __forceinline__ uint32_t tile_px(const TileIO& io, int b) {
+  return __builtin_amdgcn_raw_buffer_load_b32(io.px, io.px_lane + 16 * b, 0, 0);
+}
+
+// Byte offsets in y of the coefficients of zigzag ranks zr[c] of block b, or
+// an out-of-range offset for ranks at or beyond the block's k.
+__device__ __forceinline__ void tile_y_offsets(const TileIO& io, int b, const Lane16& L, uint32_t voff[4]) {
+  const int kk = __builtin_amdgcn_readlane(io.k, b);
+  const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(io.rel_lo, b);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) voff[c] = (L.zr[c] < kk) ? rel4 + 4u * (uint32_t)L.zr[c] : 0xffffffffu;
 }
 
 // Order the wave's LDS writes before its following LDS reads (and reads before
@@ -109,22 +138,34 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
 // (r ascending), every product and sum rounded on its own.  Used to settle
 // DD threshold decisions that the float32 path cannot decide.  `words` is the
 // block staged in LDS in the transform's operand layout: word 16g + r holds
-// pixels (r, 4g .. 4g+3), one per byte; `D` is the float64 basis.
+// pixels (r, 4g .. 4g+3), one per byte; `D` is the float64 basis.  The 16 row
+// sums are independent and advance together, so the dependent chain is 16 + 16
+// additions long.
 __device__ __attribute__((noinline)) double dct16_coef_f64(const uint32_t* words, const double* D, int u, int v) {
 #pragma clang fp contract(off)
-  double c = 0.0;
-  for (int r = 0; r < 16; ++r) {
-    double t = 0.0;
+  double t[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const double x = (double)((words[(j >> 2) * 16 + r] >> (8 * (j & 3))) & 0xffu);
-      const double p = x * D[v * 16 + j];
-      t = t + p;
+  for (int r = 0; r < 16; ++r) t[r] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t w = words[q * 16 + r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double x = (double)((w >> (8 * c)) & 0xffu);
+        const double p = x * D[v * 16 + 4 * q + c];
+        t[r] = t[r] + p;
+      }
     }
-    const double q = D[u * 16 + r] * t;
-    c = c + q;
   }
-  return c;
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const double p = D[u * 16 + r] * t[r];
+    acc = acc + p;
+  }
+  return acc;
 }
 
 }  // namespace abcs
