@@ -148,6 +148,29 @@ int abcs_sense(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes,
 int abcs_reconstruct(const abcs_plan* plan, const float* d_y, const int32_t* d_k,
                      const int64_t* d_offsets, float* d_out, void* stream);
 
+/* IDA post-processing (Section VI; eqs 13, 15, 25, 28; Fig 6).
+ * Starting from x^0 = 0 and z^{-1} = 0, iteration t = 0 .. iters-1 computes
+ *   z^t       = y - A x^t + z^{t-1} / D_F
+ *   sigma^t   = ||z^t||_2 / sqrt(m)            (per image, m = its n_meas)
+ *   x^{t+1}   = D_{sigma^t}(x^t + A* z^t)
+ * where A is the block-diagonal zigzag-DCT sensing operator of eq 26 (the
+ * first k_i DCT basis functions of block i in zigzag order) and D the chosen
+ * denoiser.  Decoder side: needs only y, k, offsets and the plan's geometry.
+ * d_x:           out, float[pixels]: x^iters, each image H' x W' (row pitch W'),
+ *                16-byte aligned.  Nothing is clipped.
+ * d_sigma_trace: out, nullable, float[iters * n]: sigma^t of image i at
+ *                t * n + i.
+ * damping:       D_F >= 1 (D_F = 1 is undamped; +inf gives z^{t-1} weight 0).
+ * denoiser:      abcs_denoiser; d_params its parameters (NULL unless CNN).
+ * d_ws:          workspace of at least ida_workspace_bytes(plan, denoiser)
+ *                bytes, 256-byte aligned; overwritten.
+ * Errors: EINVAL, EDOMAIN (D_F < 1 or NaN), EUNSUPPORTED (denoiser not
+ * built), ENOSPACE (workspace too small), EHIP. */
+size_t ida_workspace_bytes(const abcs_plan* plan, int denoiser);
+int ida_refine(const abcs_plan* plan, const float* d_y, const int32_t* d_k, const int64_t* d_offsets,
+               int iters, double damping, int denoiser, const void* d_params, float* d_x,
+               float* d_sigma_trace, void* d_ws, size_t ws_bytes, void* stream);
+
 /* Host copy of the float64 orthonormal DCT-II basis the library uses,
  * D[u*B + j] = s_u cos((2j+1) u pi / (2B)), for checking.  B in {8, 16, 32}. */
 int abcs_dct_basis(int block, double* h_out);

@@ -7,4 +7,4 @@ runs in the gfx950 kernels of libabcs.so.  There is no CPU fallback: calls
 raise if the library is missing.
 """
 from .api import (ZZ, BBV, DD, Plan, AbcsError, budget, sense, reconstruct,  # noqa: F401
-                  dct_basis, METHODS)
+                  dct_basis, METHODS, ida_refine, ida_workspace_bytes, DENOISERS)

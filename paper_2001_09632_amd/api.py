@@ -90,6 +90,26 @@ def reconstruct(plan, y, k, offsets, out, stream=None):
                                  _stream(stream)))
 
 
+IDENTITY, BM3D, CNN = 0, 1, 2
+DENOISERS = {"identity": IDENTITY, "bm3d": BM3D, "cnn": CNN}
+
+
+def ida_workspace_bytes(plan, denoiser):
+    d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
+    return int(lib().ida_workspace_bytes(plan.handle, d))
+
+
+def ida_refine(plan, y, k, offsets, x, iters, damping=2.0, denoiser="identity", params=None,
+               sigma_trace=None, workspace=None, stream=None):
+    """ida_refine: x float32[pixels] (written with x^iters); workspace a
+    uint8 device tensor of at least ida_workspace_bytes(plan, denoiser)."""
+    d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().ida_refine(plan.handle, _ptr(y), _ptr(k), _ptr(offsets), int(iters), float(damping), d,
+                           _ptr(params), _ptr(x), _ptr(sigma_trace), _ptr(workspace), ws_bytes,
+                           _stream(stream)))
+
+
 def dct_basis(block):
     """Host float64 DCT-II basis used by the library (B x B nested list)."""
     buf = (ctypes.c_double * (block * block))()

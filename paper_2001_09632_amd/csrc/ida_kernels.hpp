@@ -1,0 +1,117 @@
+// IDA post-processing (Section VI): the transform half of one iteration and
+// the per-image noise-level estimate.
+//
+// With A the block-diagonal zigzag-DCT operator (eq 26), alpha = 1/D_F (eq 28)
+// and x^0 = 0, z^{-1} = 0, iteration t computes
+//   z^t     = y - A x^t + alpha z^{t-1}          (eqs 25, 28)
+//   sigma^t = ||z^t||_2 / sqrt(m)                 (eq 15)
+//   v^t     = x^t + A* z^t                        (eq 13, before the denoiser)
+// and the denoiser then maps v^t to x^{t+1}.  In the DCT domain of a block,
+// with C = D x D^T, the measured coefficients become C + z and the others
+// stay C, so v = D^T (C + scatter(z)) D: one forward and one inverse
+// transform per block.
+#pragma once
+
+#include "common.hpp"
+#include "transform16.hpp"
+
+namespace abcs {
+
+// One wavefront per tile.  x and v are H' x W' float32 images (row pitch W');
+// z (in: z^{t-1}, out: z^t) is laid out like y; part[blk] receives the block's
+// sum of (z^t)^2 in float64, summed in a fixed order.  When `first` is set,
+// x^0 = 0 and z^{-1} = 0 are used without reading x or z.  v may alias x.
+__global__ __launch_bounds__(kGroupThreads) void k_ida_step16(const ImgDev* __restrict__ imgs,
+                                                             const Tile* __restrict__ tiles, int ntiles,
+                                                             const float* __restrict__ y,
+                                                             const int32_t* __restrict__ k_all,
+                                                             const int64_t* __restrict__ off_all,
+                                                             const float* x, float* __restrict__ z,
+                                                             float* v, double* __restrict__ part,
+                                                             float alpha, int first) {
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= ntiles) return;
+  const Tile tl = tiles[wave];
+  const ImgDev im = imgs[tl.img];
+  Lane16 L;
+  lane16_init(L);
+  TileIO io;
+  tile_io_init(io, im, tl, nullptr, y, k_all, off_all, L);
+  const __amdgpu_buffer_rsrc_t rz = make_rsrc(z + im.meas_off, (int)(4 * im.n_meas));
+  const int lane = threadIdx.x & 63;
+  // x and v: the lane's 4 pixels of row n of block b sit at float offset
+  // out_base + n W' + 16 b + 4g.
+  const int ext = 4 * (15 * im.Wc + 16 * tl.count);
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(x + tl.out_base, first ? 0 : ext);
+  const __amdgpu_buffer_rsrc_t rv = make_rsrc(v + tl.out_base, ext);
+  const uint32_t px_off = 4u * (uint32_t)(L.n * im.Wc + 4 * L.g);
+  typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+  double my_part = 0.0;  // lane b keeps block b's sum
+#pragma unroll 2
+  for (int b = 0; b < kTileBlocks; ++b) {
+    const bool valid = b < tl.count;
+    // Forward transform of x^t (0 on the first iteration: empty resource).
+    const u32x4 xw = __builtin_amdgcn_raw_buffer_load_b128(rx, valid ? px_off + 64u * b : 0xffffffffu, 0, 0);
+    float a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = __uint_as_float(xw[c]);
+    f32x4 C = dct16_fwd(a, L);
+    uint32_t voff[4];
+    tile_y_offsets(io, b, L, voff);
+    float zz = 0.f;
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float yv = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(io.y, voff[r], 0, 0));
+      const float zo = first ? 0.f : __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rz, voff[r], 0, 0));
+      // residual r = y - (A x) plus the damped previous residual
+      const float zn = (yv - C[r]) + alpha * zo;
+      // out-of-budget ranks have offset ~0 and y = z = 0 there; keep them out
+      const bool meas = voff[r] != 0xffffffffu;
+      zz = meas ? zn : 0.f;
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(zz), rz, voff[r], 0, 0);
+      C[r] = C[r] + zz;
+      acc += (double)zz * (double)zz;
+    }
+    // Fixed-order butterfly sum over the wave.
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == b) my_part = acc;
+    float e[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) e[c] = C[c];
+    const f32x4 X = idct16_inv(e, L);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X), rv, valid ? px_off + 64u * b : 0xffffffffu,
+                                           0, 0);
+  }
+  if (lane < tl.count) part[im.blk_off + tl.first + lane] = my_part;
+}
+
+// sigma_i = sqrt(sum of the image's block partials / m_i), one workgroup per
+// image; partials are added in block order by a fixed tree.  Also appends
+// sigma to trace[t * n + i] when trace is not null.
+__global__ __launch_bounds__(kGroupThreads) void k_ida_sigma(const ImgDev* __restrict__ imgs,
+                                                            const double* __restrict__ part,
+                                                            float* __restrict__ sigma, float* __restrict__ trace,
+                                                            int n_imgs, int t) {
+  __shared__ double sh[kGroupThreads];
+  const ImgDev im = imgs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int per = (im.nB + kGroupThreads - 1) / kGroupThreads;
+  const int i0 = min(im.nB, tid * per), i1 = min(im.nB, i0 + per);
+  double s = 0.0;
+  for (int i = i0; i < i1; ++i) s += part[im.blk_off + i];
+  sh[tid] = s;
+  __syncthreads();
+  for (int w = kGroupThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const float sg = im.n_meas > 0 ? (float)sqrt(sh[0] / (double)im.n_meas) : 0.f;
+    sigma[blockIdx.x] = sg;
+    if (trace) trace[(int64_t)t * n_imgs + blockIdx.x] = sg;
+  }
+}
+
+}  // namespace abcs

@@ -5,4 +5,5 @@
 #include "transform16.hpp"
 #include "budget_kernels.hpp"
 #include "sense_kernels.hpp"
+#include "ida_kernels.hpp"
 #include "api.cpp.inc"
