@@ -171,6 +171,22 @@ int ida_refine(const abcs_plan* plan, const float* d_y, const int32_t* d_k, cons
                int iters, double damping, int denoiser, const void* d_params, float* d_x,
                float* d_sigma_trace, void* d_ws, size_t ws_bytes, void* stream);
 
+/* Apply an IDA denoiser D_sigma to every image of a plan (the step
+ * x^{t+1} = D_sigma(v^t) of ida_refine, exposed on its own).
+ * d_in, d_out: float[pixels], each image H' x W' with row pitch W', 16-byte
+ *              aligned; must not alias except for the identity.
+ * d_sigma:     float[n], the noise level of each image (sigma <= 0 returns the
+ *              image unchanged).
+ * BM3D follows Dabov et al. (ref [22]) with 8x8 patches, step 3, 39x39
+ * search, groups of at most 16 / 32 (thresholds 2500 / 400 on ||P-Q||^2/64),
+ * 8x8 DCT + Haar 3D transform, hard threshold 2.7 sigma, Wiener second stage,
+ * Kaiser (beta 2) aggregation; results are bit-identical from run to run.
+ * d_ws: workspace of abcs_denoise_workspace_bytes(plan, denoiser) bytes,
+ * 256-byte aligned (NULL allowed when that is 0). */
+size_t abcs_denoise_workspace_bytes(const abcs_plan* plan, int denoiser);
+int abcs_denoise(const abcs_plan* plan, int denoiser, const void* d_params, const float* d_in,
+                 const float* d_sigma, float* d_out, void* d_ws, size_t ws_bytes, void* stream);
+
 /* Host copy of the float64 orthonormal DCT-II basis the library uses,
  * D[u*B + j] = s_u cos((2j+1) u pi / (2B)), for checking.  B in {8, 16, 32}. */
 int abcs_dct_basis(int block, double* h_out);

@@ -110,6 +110,19 @@ def ida_refine(plan, y, k, offsets, x, iters, damping=2.0, denoiser="identity", 
                            _stream(stream)))
 
 
+def denoise_workspace_bytes(plan, denoiser):
+    d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
+    return int(lib().abcs_denoise_workspace_bytes(plan.handle, d))
+
+
+def denoise(plan, x_in, sigma, x_out, denoiser="bm3d", params=None, workspace=None, stream=None):
+    """abcs_denoise: x_in, x_out float32[pixels]; sigma float32[n] device tensors."""
+    d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().abcs_denoise(plan.handle, d, _ptr(params), _ptr(x_in), _ptr(sigma), _ptr(x_out),
+                             _ptr(workspace), ws_bytes, _stream(stream)))
+
+
 def dct_basis(block):
     """Host float64 DCT-II basis used by the library (B x B nested list)."""
     buf = (ctypes.c_double * (block * block))()

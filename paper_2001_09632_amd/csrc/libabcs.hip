@@ -6,4 +6,5 @@
 #include "budget_kernels.hpp"
 #include "sense_kernels.hpp"
 #include "ida_kernels.hpp"
+#include "bm3d_kernels.hpp"
 #include "api.cpp.inc"
