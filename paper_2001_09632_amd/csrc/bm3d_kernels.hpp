@@ -149,36 +149,53 @@ __global__ __launch_bounds__(256) void k_bm3d_match(const ImgDev* __restrict__ i
 }
 
 // ---------------------------------------------------------------------------
-// Collaborative filtering of the groups, one wavefront per reference; lane
-// (r, c) = (lane / 8, lane % 8) owns pixel (r, c) of every member patch and,
-// in the spectrum, coefficient (u, v) = (r, c) of every member.
+// Collaborative filtering of the groups of an 8x8-reference tile, one
+// wavefront per reference at a time; lane (r, c) = (lane / 8, lane % 8) owns
+// pixel (r, c) of every member patch and, in the spectrum, coefficient
+// (u, v) = (r, c) of every member.  Contributions are summed in LDS over the
+// tile's window (every member lies within 19 pixels of its reference) and the
+// window is added to the image's accumulators once.
 // ---------------------------------------------------------------------------
+constexpr int kFiltTile = 8;
+constexpr int kFiltWin = (kFiltTile - 1) * bm3d::kStep + 2 * bm3d::kHalfWin + bm3d::kN1;  // 67
+
+struct Dct8Lane {
+  float f1[8], f2[8], i1[8], i2[8];
+};
+
+__device__ __forceinline__ void dct8_lane_init(Dct8Lane& d, int r, int c) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    d.f1[j] = c_D8[c * 8 + j];   // D[v = c][j]
+    d.f2[j] = c_D8[r * 8 + j];   // D[u = r][i]
+    d.i1[j] = c_D8[j * 8 + c];   // D[v][j = c]
+    d.i2[j] = c_D8[j * 8 + r];   // D[u][i = r]
+  }
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // 8x8 DCT (or its inverse) of one patch held one value per lane, through LDS.
-__device__ __forceinline__ float dct8_lane(float x, float* sh, int r, int c, bool inverse) {
+//  forward: T[r][v] = sum_j X[r][j] D[v][j];  C[u][v] = sum_i D[u][i] T[i][v]
+//  inverse: T[u][j] = sum_v C[u][v] D[v][j];  X[i][j] = sum_u D[u][i] T[u][j]
+__device__ __forceinline__ float dct8_lane(float x, float* sh, int r, int c, const Dct8Lane& d, bool inverse) {
   const int lane = threadIdx.x & 63;
   sh[lane] = x;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // forward: T[r][v] = sum_j X[r][j] D[v][j]; inverse: T[r][j] = sum_v C[r][v] D[v][j]
+  wave_sync_lds();
   float t = 0.f;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) t = fmaf(sh[r * 8 + j], inverse ? c_D8[j * 8 + c] : c_D8[c * 8 + j], t);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int j = 0; j < 8; ++j) t = fmaf(sh[r * 8 + j], inverse ? d.i1[j] : d.f1[j], t);
+  wave_sync_lds();
   sh[lane] = t;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // forward: C[u][v] = sum_i D[u][i] T[i][v]; inverse: X[i][j] = sum_u D[u][i] T[u][j]
+  wave_sync_lds();
   float o = 0.f;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) o = fmaf(inverse ? c_D8[i * 8 + r] : c_D8[r * 8 + i], sh[i * 8 + c], o);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int i = 0; i < 8; ++i) o = fmaf(inverse ? d.i2[i] : d.f2[i], sh[i * 8 + c], o);
+  wave_sync_lds();
   return o;
 }
 
@@ -222,9 +239,7 @@ __device__ __forceinline__ void haar_inv(float* s, int n) {
   }
 }
 
-__device__ __forceinline__ void fix_add(unsigned long long* p, double v) {
-  atomicAdd(p, (unsigned long long)(long long)llrint(v * bm3d::kFix));
-}
+__device__ __forceinline__ long long to_fix(double v) { return (long long)llrint(v * bm3d::kFix); }
 
 // STAGE 1: hard thresholding of groups cut from `noisy`.
 // STAGE 2: Wiener shrinkage of groups cut from `noisy` with the spectrum of
@@ -238,36 +253,53 @@ __global__ __launch_bounds__(256) void k_bm3d_filter(const ImgDev* __restrict__ 
                                                     unsigned long long* __restrict__ den) {
   using namespace bm3d;
   constexpr int N2 = STAGE == 1 ? kN2Ht : kN2Wie;
+  __shared__ unsigned long long acc_num[kFiltWin * kFiltWin];
+  __shared__ unsigned long long acc_den[kFiltWin * kFiltWin];
   __shared__ float sh[4][64];
   if ((int)blockIdx.x >= ntiles) return;
   const RefTile tl = tiles[blockIdx.x];
   const ImgDev im = imgs[tl.img];
   const float sg = sigma[tl.img];
   if (!(sg > 0.f)) return;
-  const int W = im.Wc;
+  const int H = im.Hc, W = im.Wc;
+  // window of the tile: all member patches of its groups lie inside
+  const int wy0 = max(0, bm3d_ref_pos(tl.i0, H) - kHalfWin);
+  const int wx0 = max(0, bm3d_ref_pos(tl.j0, W) - kHalfWin);
+  const int wy1 = min(H - kN1, bm3d_ref_pos(tl.i0 + tl.ni - 1, H) + kHalfWin) + kN1;
+  const int wx1 = min(W - kN1, bm3d_ref_pos(tl.j0 + tl.nj - 1, W) + kHalfWin) + kN1;
+  const int wh = wy1 - wy0, ww = wx1 - wx0;
+  for (int t = threadIdx.x; t < kFiltWin * kFiltWin; t += 256) {
+    acc_num[t] = 0ull;
+    acc_den[t] = 0ull;
+  }
+  __syncthreads();
   const int wave = wave_in_group();
   float* shw = sh[wave];
   const int lane = threadIdx.x & 63, r = lane >> 3, c = lane & 7;
+  Dct8Lane dl;
+  dct8_lane_init(dl, r, c);
   const float K = c_kaiser8[lane];
   const int nrw = bm3d_nref(W);
   for (int q = wave; q < tl.ni * tl.nj; q += 4) {
     const int ti = q / tl.nj, tj = q - ti * tl.nj;
     const int32_t* g = groups + (tl.ref_base + (int64_t)ti * nrw + tj) * (N2 + 1);
     const int n = g[0];
-    int pos[N2];
+    int loc[N2];
     float s[N2], b[N2];
 #pragma unroll
     for (int j = 0; j < N2; ++j) {
-      pos[j] = j < n ? g[1 + j] : 0;
-      const int64_t a = im.out_off + pos[j] + r * W + c;
+      const int pos = j < n ? g[1 + j] : 0;
+      const int py = pos / W, px = pos - py * W;
+      loc[j] = (py - wy0 + r) * kFiltWin + (px - wx0 + c);
+      const int64_t a = im.out_off + pos + r * W + c;
       s[j] = j < n ? noisy[a] : 0.f;
       if (STAGE == 2) b[j] = j < n ? basic[a] : 0.f;
     }
 #pragma unroll
     for (int j = 0; j < N2; ++j) {
       if (j < n) {
-        s[j] = dct8_lane(s[j], shw, r, c, false);
-        if (STAGE == 2) b[j] = dct8_lane(b[j], shw, r, c, false);
+        s[j] = dct8_lane(s[j], shw, r, c, dl, false);
+        if (STAGE == 2) b[j] = dct8_lane(b[j], shw, r, c, dl, false);
       }
     }
     haar_fwd<N2>(s, n);
@@ -302,14 +334,24 @@ __global__ __launch_bounds__(256) void k_bm3d_filter(const ImgDev* __restrict__ 
       wgt = 1.0 / (double)(w2 > kWFloor ? w2 : kWFloor);
     }
     haar_inv<N2>(s, n);
+    const unsigned long long dk = (unsigned long long)to_fix(wgt * (double)K);
 #pragma unroll
     for (int j = 0; j < N2; ++j) {
       if (j < n) {
-        const float e = dct8_lane(s[j], shw, r, c, true);
-        const int64_t a = im.out_off + pos[j] + r * W + c;
-        fix_add(num + a, wgt * (double)K * (double)e);
-        fix_add(den + a, wgt * (double)K);
+        const float e = dct8_lane(s[j], shw, r, c, dl, true);
+        atomicAdd(&acc_num[loc[j]], (unsigned long long)to_fix(wgt * (double)K * (double)e));
+        atomicAdd(&acc_den[loc[j]], dk);
       }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < wh * ww; t += 256) {
+    const int rr = t / ww, cc = t - rr * ww;
+    const unsigned long long dv = acc_den[rr * kFiltWin + cc];
+    if (dv != 0ull) {
+      const int64_t a = im.out_off + (int64_t)(wy0 + rr) * W + wx0 + cc;
+      atomicAdd(num + a, acc_num[rr * kFiltWin + cc]);
+      atomicAdd(den + a, dv);
     }
   }
 }
