@@ -62,9 +62,12 @@ __device__ __forceinline__ int bm3d_nref(int len) {
 
 // ---------------------------------------------------------------------------
 // Block matching.  One thread per reference; the tile's search area is staged
-// in LDS.  Candidates are visited in raster order of their position and a
-// candidate enters the sorted list only if strictly closer than the current
-// last entry, so equal distances keep the lower raster index first.
+// in LDS (zero outside the image).  For each candidate row offset the thread
+// streams each of the 8 patch rows' 46-pixel search segment once and adds its
+// squared differences to the 39 candidate columns' sums, so every LDS value
+// serves up to 8 candidates.  Candidates are then offered in raster order of
+// their position and enter the sorted list only if strictly closer than the
+// current last entry, so equal distances keep the lower raster index first.
 // groups[ref * (N2 + 1)] = member count (power of two), then member positions
 // (row * W' + col) in group order.
 // ---------------------------------------------------------------------------
@@ -74,6 +77,8 @@ __global__ __launch_bounds__(256) void k_bm3d_match(const ImgDev* __restrict__ i
                                                    const float* __restrict__ sigma, float tau,
                                                    int32_t* __restrict__ groups) {
   using namespace bm3d;
+  constexpr int kSpan = 2 * kHalfWin + 1;    // 39 candidate offsets per axis
+  constexpr int kSeg = kSpan + kN1 - 1;      // 46 pixels per search row
   __shared__ float win[kWin * kWin];
   if ((int)blockIdx.x >= ntiles) return;
   const RefTile tl = tiles[blockIdx.x];
@@ -81,25 +86,20 @@ __global__ __launch_bounds__(256) void k_bm3d_match(const ImgDev* __restrict__ i
   if (!(sigma[tl.img] > 0.f)) return;
   const int H = im.Hc, W = im.Wc;
   const float* img = src + im.out_off;
-  // Window rows/cols covered by the tile's search areas (patch origins).
-  const int ry0 = bm3d_ref_pos(tl.i0, H), ry1 = bm3d_ref_pos(tl.i0 + tl.ni - 1, H);
-  const int rx0 = bm3d_ref_pos(tl.j0, W), rx1 = bm3d_ref_pos(tl.j0 + tl.nj - 1, W);
-  const int wy0 = max(0, ry0 - kHalfWin), wy1 = min(H - kN1, ry1 + kHalfWin) + kN1;  // exclusive
-  const int wx0 = max(0, rx0 - kHalfWin), wx1 = min(W - kN1, rx1 + kHalfWin) + kN1;
-  const int wh = wy1 - wy0, ww = wx1 - wx0;
-  for (int t = threadIdx.x; t < wh * ww; t += 256) {
-    const int r = t / ww, c = t - r * ww;
-    win[r * kWin + c] = img[(int64_t)(wy0 + r) * W + wx0 + c];
+  // Unclipped window of the tile: row/col wy0 + r of LDS is image row
+  // wy0 + r (zero when outside the image).
+  const int wy0 = bm3d_ref_pos(tl.i0, H) - kHalfWin;
+  const int wx0 = bm3d_ref_pos(tl.j0, W) - kHalfWin;
+  for (int t = threadIdx.x; t < kWin * kWin; t += 256) {
+    const int r = t / kWin, c = t - r * kWin;
+    const int y = wy0 + r, x = wx0 + c;
+    win[t] = (y >= 0 && y < H && x >= 0 && x < W) ? img[(int64_t)y * W + x] : 0.f;
   }
   __syncthreads();
   const int ti = threadIdx.x / kRefTile, tj = threadIdx.x % kRefTile;
   if (ti >= tl.ni || tj >= tl.nj) return;
   const int ry = bm3d_ref_pos(tl.i0 + ti, H), rx = bm3d_ref_pos(tl.j0 + tj, W);
-  float ref[kN1 * kN1];
-#pragma unroll
-  for (int r = 0; r < kN1; ++r)
-#pragma unroll
-    for (int c = 0; c < kN1; ++c) ref[r * kN1 + c] = win[(ry - wy0 + r) * kWin + (rx - wx0 + c)];
+  const float* refp = win + (ry - wy0) * kWin + (rx - wx0);  // reference patch, read row by row
   float bd[N2];
   int bi[N2];
   bd[0] = -1.f;  // the reference itself leads the group
@@ -112,18 +112,34 @@ __global__ __launch_bounds__(256) void k_bm3d_match(const ImgDev* __restrict__ i
   const int qy0 = max(0, ry - kHalfWin), qy1 = min(H - kN1, ry + kHalfWin);
   const int qx0 = max(0, rx - kHalfWin), qx1 = min(W - kN1, rx + kHalfWin);
   for (int qy = qy0; qy <= qy1; ++qy) {
-    for (int qx = qx0; qx <= qx1; ++qx) {
-      float ssd = 0.f;
-      const float* cp = win + (qy - wy0) * kWin + (qx - wx0);
+    float acc[kSpan];
 #pragma unroll
-      for (int r = 0; r < kN1; ++r)
+    for (int q = 0; q < kSpan; ++q) acc[q] = 0.f;
+    const float* rowp = win + (qy - wy0) * kWin + (rx - kHalfWin - wx0);
+#pragma unroll 1
+    for (int r = 0; r < kN1; ++r) {
+      const float* seg = rowp + r * kWin;
+      float rr[kN1];
+#pragma unroll
+      for (int c = 0; c < kN1; ++c) rr[c] = refp[r * kWin + c];
+#pragma unroll
+      for (int j = 0; j < kSeg; ++j) {
+        const float pj = seg[j];
 #pragma unroll
         for (int c = 0; c < kN1; ++c) {
-          const float dlt = ref[r * kN1 + c] - cp[r * kWin + c];
-          ssd = fmaf(dlt, dlt, ssd);
+          const int q = j - c;  // candidate column offset using pixel j at patch column c
+          if (q >= 0 && q < kSpan) {
+            const float dlt = rr[c] - pj;
+            acc[q] = fmaf(dlt, dlt, acc[q]);
+          }
         }
-      const float d = ssd * (1.0f / 64.f);
-      if (d <= tau && d < bd[N2 - 1] && !(qy == ry && qx == rx)) {
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kSpan; ++q) {
+      const int qx = rx - kHalfWin + q;
+      const float d = acc[q] * (1.0f / 64.f);
+      if (qx >= qx0 && qx <= qx1 && d <= tau && d < bd[N2 - 1] && !(qy == ry && qx == rx)) {
         const int idx = qy * W + qx;
         // insert keeping (d, raster index) order; earlier equal d stay first
 #pragma unroll
