@@ -184,6 +184,15 @@ int ida_refine(const abcs_plan* plan, const float* d_y, const int32_t* d_k, cons
  * d_ws: workspace of abcs_denoise_workspace_bytes(plan, denoiser) bytes,
  * 256-byte aligned (NULL allowed when that is 0). */
 size_t abcs_denoise_workspace_bytes(const abcs_plan* plan, int denoiser);
+/* Number of float32 values in the CNN parameter blob (223361).  The blob
+ * holds, layer after layer (2->64, six 64->64, 64->1 channels, 3x3 kernels),
+ * the weights [C_out][3][3][C_in] followed by the biases [C_out].  The
+ * network maps an image v and its noise level sigma to
+ * v - 255 f([v/255, min(sigma,255)/255]); ReLU after layers 1..7, zero
+ * padding; weights and activations are rounded to bfloat16, sums are float32.
+ * A stand-in for the paper's DnCNN (Section VI-4), whose weights are not
+ * available; trained with abcs_cnn_train_step. */
+size_t abcs_cnn_param_count(void);
 int abcs_denoise(const abcs_plan* plan, int denoiser, const void* d_params, const float* d_in,
                  const float* d_sigma, float* d_out, void* d_ws, size_t ws_bytes, void* stream);
 

@@ -12,6 +12,7 @@ EXPORTS = [
     "abcs_plan_create", "abcs_plan_destroy", "abcs_plan_totals", "abcs_plan_image",
     "abcs_budget", "abcs_sense", "abcs_reconstruct", "abcs_dct_basis", "abcs_last_error",
     "ida_workspace_bytes", "ida_refine", "abcs_denoise_workspace_bytes", "abcs_denoise",
+    "abcs_cnn_param_count",
 ]
 
 
@@ -42,6 +43,11 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2001_09632_amd.build`")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7 and the
+    # library's dependency of the same name must resolve to it, so torch is
+    # loaded first (loading the library first would bind torch to the system
+    # runtime instead, and torch then finds no GPU).
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
     P64 = ctypes.POINTER(ctypes.c_int64)
@@ -61,10 +67,12 @@ def lib():
     L.abcs_denoise_workspace_bytes.argtypes = [vp, i32]
     L.abcs_denoise_workspace_bytes.restype = sz
     L.abcs_denoise.argtypes = [vp, i32, vp, vp, vp, vp, vp, sz, vp]
+    L.abcs_cnn_param_count.argtypes = []
+    L.abcs_cnn_param_count.restype = sz
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("abcs_plan_destroy", "abcs_last_error", "ida_workspace_bytes",
-                        "abcs_denoise_workspace_bytes"):
+                        "abcs_denoise_workspace_bytes", "abcs_cnn_param_count"):
             f.restype = ctypes.c_int
     _lib = L
     return L

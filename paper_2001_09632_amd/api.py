@@ -123,6 +123,10 @@ def denoise(plan, x_in, sigma, x_out, denoiser="bm3d", params=None, workspace=No
                              _ptr(workspace), ws_bytes, _stream(stream)))
 
 
+def cnn_param_count():
+    return int(lib().abcs_cnn_param_count())
+
+
 def dct_basis(block):
     """Host float64 DCT-II basis used by the library (B x B nested list)."""
     buf = (ctypes.c_double * (block * block))()

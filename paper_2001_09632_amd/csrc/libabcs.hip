@@ -7,4 +7,5 @@
 #include "sense_kernels.hpp"
 #include "ida_kernels.hpp"
 #include "bm3d_kernels.hpp"
+#include "cnn_kernels.hpp"
 #include "api.cpp.inc"
