@@ -193,6 +193,22 @@ size_t abcs_denoise_workspace_bytes(const abcs_plan* plan, int denoiser);
  * A stand-in for the paper's DnCNN (Section VI-4), whose weights are not
  * available; trained with abcs_cnn_train_step. */
 size_t abcs_cnn_param_count(void);
+
+/* One training step of the CNN on a batch described by a plan (its images'
+ * geometry only: method, subrate and pixel fields are not used).
+ * d_input, d_target: float[pixels] (plan layout) network input v and the
+ *                    clean image; d_sigma: float[n] noise level per image.
+ * Loss: mean over all pixels of ((D(v) - target) / 255)^2, written to
+ * d_loss[0].  Gradients of the loss w.r.t. every parameter (bfloat16
+ * activations, float32 sums, fixed summation order) are written to d_grad
+ * (float[param_count], nullable).  When lr > 0, Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias correction for `step` >= 1) updates d_params (float32 master
+ * weights) with moments d_adam_m, d_adam_v (float[param_count], zero before
+ * the first step).  d_ws: abcs_cnn_train_workspace_bytes(plan) bytes. */
+size_t abcs_cnn_train_workspace_bytes(const abcs_plan* plan);
+int abcs_cnn_train_step(const abcs_plan* plan, float* d_params, float* d_adam_m, float* d_adam_v, int64_t step,
+                        float lr, const float* d_input, const float* d_sigma, const float* d_target,
+                        float* d_loss, float* d_grad, void* d_ws, size_t ws_bytes, void* stream);
 int abcs_denoise(const abcs_plan* plan, int denoiser, const void* d_params, const float* d_in,
                  const float* d_sigma, float* d_out, void* d_ws, size_t ws_bytes, void* stream);
 

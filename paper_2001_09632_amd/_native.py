@@ -12,7 +12,7 @@ EXPORTS = [
     "abcs_plan_create", "abcs_plan_destroy", "abcs_plan_totals", "abcs_plan_image",
     "abcs_budget", "abcs_sense", "abcs_reconstruct", "abcs_dct_basis", "abcs_last_error",
     "ida_workspace_bytes", "ida_refine", "abcs_denoise_workspace_bytes", "abcs_denoise",
-    "abcs_cnn_param_count",
+    "abcs_cnn_param_count", "abcs_cnn_train_workspace_bytes", "abcs_cnn_train_step",
 ]
 
 
@@ -69,10 +69,14 @@ def lib():
     L.abcs_denoise.argtypes = [vp, i32, vp, vp, vp, vp, vp, sz, vp]
     L.abcs_cnn_param_count.argtypes = []
     L.abcs_cnn_param_count.restype = sz
+    L.abcs_cnn_train_workspace_bytes.argtypes = [vp]
+    L.abcs_cnn_train_workspace_bytes.restype = sz
+    L.abcs_cnn_train_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp, vp, vp, vp, vp, vp, sz, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("abcs_plan_destroy", "abcs_last_error", "ida_workspace_bytes",
-                        "abcs_denoise_workspace_bytes", "abcs_cnn_param_count"):
+                        "abcs_denoise_workspace_bytes", "abcs_cnn_param_count",
+                        "abcs_cnn_train_workspace_bytes"):
             f.restype = ctypes.c_int
     _lib = L
     return L

@@ -127,6 +127,20 @@ def cnn_param_count():
     return int(lib().abcs_cnn_param_count())
 
 
+def cnn_train_workspace_bytes(plan):
+    return int(lib().abcs_cnn_train_workspace_bytes(plan.handle))
+
+
+def cnn_train_step(plan, params, adam_m, adam_v, step, lr, x_in, sigma, target, loss, grad=None,
+                   workspace=None, stream=None):
+    """abcs_cnn_train_step on device tensors (float32); updates params, adam_m,
+    adam_v in place when lr > 0; loss float32[1]; grad float32[params] or None."""
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().abcs_cnn_train_step(plan.handle, _ptr(params), _ptr(adam_m), _ptr(adam_v), int(step),
+                                    float(lr), _ptr(x_in), _ptr(sigma), _ptr(target), _ptr(loss), _ptr(grad),
+                                    _ptr(workspace), ws_bytes, _stream(stream)))
+
+
 def dct_basis(block):
     """Host float64 DCT-II basis used by the library (B x B nested list)."""
     buf = (ctypes.c_double * (block * block))()

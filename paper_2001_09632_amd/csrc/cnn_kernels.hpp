@@ -249,4 +249,267 @@ __global__ __launch_bounds__(256) void k_cnn_last(const ImgDev* __restrict__ img
   out[p] = v[p] - 255.f * f;
 }
 
+// ---------------------------------------------------------------------------
+// Training: loss, gradients, Adam.  The loss is the mean over the batch's
+// pixels of ((D(v) - target) / 255)^2; df = dL/df = -2 (D(v) - target) / (255 n)
+// since D(v) = v - 255 f.
+// ---------------------------------------------------------------------------
+
+// df and one partial loss sum per 256-pixel block (fixed order).
+__global__ __launch_bounds__(256) void k_cnn_loss(const float* __restrict__ out, const float* __restrict__ target,
+                                                 int64_t pixels, float* __restrict__ df,
+                                                 double* __restrict__ loss_part) {
+  __shared__ double sh[256];
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double l = 0.0;
+  if (p < pixels) {
+    const float d = (out[p] - target[p]) * (1.f / 255.f);
+    df[p] = -2.f * d / (float)pixels;
+    l = (double)d * (double)d;
+  }
+  sh[threadIdx.x] = l;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = sh[0];
+}
+
+// Sum `n` float64 partials in order into out[0] (single thread; n is small).
+__global__ void k_sum_loss(const double* __restrict__ part, int64_t n, int64_t pixels, float* __restrict__ loss) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += part[i];
+  loss[0] = (float)(s / (double)pixels);
+}
+
+// Layer-8 input gradient: dz7[q][c] = [a7[q][c] > 0] sum_tap w8[tap][c] df[q - off(tap)].
+__global__ __launch_bounds__(256) void k_cnn_last_bwd(const ImgDev* __restrict__ imgs,
+                                                     const int32_t* __restrict__ pix_img, int64_t pixels,
+                                                     const float* __restrict__ df,
+                                                     const unsigned short* __restrict__ a7,
+                                                     const float* __restrict__ w8r, unsigned short* __restrict__ dz7) {
+  using namespace cnn;
+  __shared__ float sw[9 * 64];
+  for (int t = threadIdx.x; t < 9 * 64; t += 256) sw[t] = w8r[t];
+  __syncthreads();
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= pixels) return;
+  const ImgDev im = imgs[pix_img[q >> 8]];
+  const int64_t lq = q - im.out_off;
+  const int y = (int)(lq / im.Wc), x = (int)(lq - (int64_t)y * im.Wc);
+  float d[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    // output pixel p = q - off(tap) read input q through tap
+    const int yy = y - (t / 3 - 1), xx = x - (t % 3 - 1);
+    d[t] = (yy >= 0 && yy < im.Hc && xx >= 0 && xx < im.Wc) ? df[im.out_off + (int64_t)yy * im.Wc + xx] : 0.f;
+  }
+  const u16x8* a = (const u16x8*)(a7 + q * kCh);
+  u16x8* o = (u16x8*)(dz7 + q * kCh);
+#pragma unroll
+  for (int part = 0; part < 8; ++part) {
+    const u16x8 av = a[part];
+    u16x8 ov;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int c = part * 8 + k;
+      float g = 0.f;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) g = fmaf(sw[t * 64 + c], d[t], g);
+      ov[k] = bf2f(av[k]) > 0.f ? f2bf(g) : (unsigned short)0;
+    }
+    o[part] = ov;
+  }
+}
+
+// Weight and bias gradients of layer 8 (64 -> 1):
+//   dW8[tap][c] = sum_p df[p] a7[p + off(tap)][c],  db8 = sum_p df[p].
+// Thread t of a workgroup owns outputs t, t + 256, t + 512 of the 577 and
+// walks the workgroup's pixel range; partial sums go to part[wg][577].
+__global__ __launch_bounds__(256) void k_cnn_last_wgrad(const ImgDev* __restrict__ imgs,
+                                                       const int32_t* __restrict__ pix_img, int64_t pixels,
+                                                       const float* __restrict__ df,
+                                                       const unsigned short* __restrict__ a7,
+                                                       float* __restrict__ part, int64_t chunk) {
+  using namespace cnn;
+  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(pixels, p0 + chunk);
+  float acc[3] = {0.f, 0.f, 0.f};
+  for (int64_t p = p0; p < p1; ++p) {
+    const ImgDev im = imgs[pix_img[p >> 8]];
+    const int64_t lp = p - im.out_off;
+    const int y = (int)(lp / im.Wc), x = (int)(lp - (int64_t)y * im.Wc);
+    const float dv = df[p];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int o = threadIdx.x + 256 * k;
+      if (o < 576) {
+        const int tap = o / 64, c = o % 64;
+        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+        if (yy >= 0 && yy < im.Hc && xx >= 0 && xx < im.Wc)
+          acc[k] = fmaf(dv, bf2f(a7[(im.out_off + (int64_t)yy * im.Wc + xx) * kCh + c]), acc[k]);
+      } else if (o == 576) {
+        acc[k] += dv;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int o = threadIdx.x + 256 * k;
+    if (o <= 576) part[(int64_t)blockIdx.x * 577 + o] = acc[k];
+  }
+}
+
+// Weight and bias gradients of layer 1 (2 -> 64) from dz1 and the network
+// input [v / 255, min(sigma, 255) / 255] (zero outside the image):
+// 64 x 9 x 2 weights + 64 biases = 1216 outputs, same scheme as above.
+__global__ __launch_bounds__(256) void k_cnn_first_wgrad(const ImgDev* __restrict__ imgs,
+                                                        const int32_t* __restrict__ pix_img, int64_t pixels,
+                                                        const float* __restrict__ v, const float* __restrict__ sigma,
+                                                        const unsigned short* __restrict__ dz1,
+                                                        float* __restrict__ part, int64_t chunk) {
+  using namespace cnn;
+  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(pixels, p0 + chunk);
+  float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int64_t p = p0; p < p1; ++p) {
+    const int ii = pix_img[p >> 8];
+    const ImgDev im = imgs[ii];
+    const int64_t lp = p - im.out_off;
+    const int y = (int)(lp / im.Wc), x = (int)(lp - (int64_t)y * im.Wc);
+    const float s = fminf(sigma[ii], 255.f) * (1.f / 255.f);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int o = threadIdx.x + 256 * k;
+      if (o < 1152) {
+        const int co = o / 18, tap = (o % 18) / 2, c = o % 2;
+        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+        if (yy >= 0 && yy < im.Hc && xx >= 0 && xx < im.Wc) {
+          const float in = c == 0 ? v[im.out_off + (int64_t)yy * im.Wc + xx] * (1.f / 255.f) : s;
+          acc[k] = fmaf(bf2f(dz1[p * kCh + co]), in, acc[k]);
+        }
+      } else if (o < 1216) {
+        acc[k] += bf2f(dz1[p * kCh + (o - 1152)]);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const int o = threadIdx.x + 256 * k;
+    if (o < 1216) part[(int64_t)blockIdx.x * 1216 + o] = acc[k];
+  }
+}
+
+// Weight and bias gradients of a 64 -> 64 layer on bfloat16 MFMA:
+//   dW[co][tap][ci] = sum_p dz[p][co] a[p + off(tap)][ci],  db[co] = sum_p dz[p][co]
+// as a GEMM with K = pixels.  A workgroup walks 8 x 16-pixel tiles; each tile
+// is staged transposed in LDS (dz as [co][pixel], a with its halo as three
+// column-shifted copies [dx][ci][row][col]) so that both operands are 8
+// consecutive pixels per lane.  Wave w owns input channels 16 w .. 16 w + 15
+// for all 9 taps and all 64 output channels (36 accumulators).  Partial sums
+// of the workgroup go to part[wg][36928] in blob order (weights, then bias).
+__global__ __launch_bounds__(256) void k_cnn_mid_wgrad(const ImgDev* __restrict__ imgs,
+                                                      const CnnTile* __restrict__ tiles, int ntiles,
+                                                      const unsigned short* __restrict__ dz,
+                                                      const unsigned short* __restrict__ a,
+                                                      float* __restrict__ part) {
+  using namespace cnn;
+  constexpr int NPX = kTileH * kTileW;  // 128
+  __shared__ __attribute__((aligned(16))) unsigned short dzT[64 * NPX];
+  __shared__ __attribute__((aligned(16))) unsigned short aT[3 * 64 * (kTileH + 2) * kTileW];
+  const int wave = wave_in_group();
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+  f32x4 acc[4][9];
+#pragma unroll
+  for (int cg = 0; cg < 4; ++cg)
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) acc[cg][tap] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;  // thread t < 64: bias gradient of channel t
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const CnnTile tl = tiles[ti];
+    const ImgDev im = imgs[tl.img];
+    __syncthreads();
+    // dz tile -> dzT[co][row * 16 + col]
+    for (int t = threadIdx.x; t < NPX * 8; t += 256) {
+      const int px = t >> 3, part8 = t & 7;
+      const int y = tl.y0 + px / kTileW, x = tl.x0 + px % kTileW;
+      const u16x8 val = *(const u16x8*)(dz + (im.out_off + (int64_t)y * im.Wc + x) * kCh + part8 * 8);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) dzT[(part8 * 8 + k) * NPX + px] = val[k];
+    }
+    // a tile with halo -> aT[dx][ci][row][col] = a[y0 - 1 + row][x0 - 1 + dx + col][ci]
+    for (int t = threadIdx.x; t < (kTileH + 2) * (kTileW + 2) * 8; t += 256) {
+      const int px = t >> 3, part8 = t & 7;
+      const int row = px / (kTileW + 2), col = px % (kTileW + 2);
+      const int y = tl.y0 - 1 + row, x = tl.x0 - 1 + col;
+      u16x8 val = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (y >= 0 && y < im.Hc && x >= 0 && x < im.Wc)
+        val = *(const u16x8*)(a + (im.out_off + (int64_t)y * im.Wc + x) * kCh + part8 * 8);
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int c = col - dx;
+        if (c >= 0 && c < kTileW) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            aT[((dx * 64 + part8 * 8 + k) * (kTileH + 2) + row) * kTileW + c] = val[k];
+        }
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      for (int px = 0; px < NPX; ++px) bacc += bf2f(dzT[threadIdx.x * NPX + px]);
+    }
+    // K = 128 pixels in 4 chunks of 32 (2 rows x 16 cols); lane group g
+    // covers row 2 kc + g / 2, columns 8 (g % 2) .. + 8.
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const int row = 2 * kc + (g >> 1), col = 8 * (g & 1);
+      bf16x8 av[4];
+#pragma unroll
+      for (int cg = 0; cg < 4; ++cg) av[cg] = *(const bf16x8*)(dzT + (16 * cg + n) * NPX + row * kTileW + col);
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;
+        const bf16x8 bv =
+            *(const bf16x8*)(aT + ((dx * 64 + 16 * wave + n) * (kTileH + 2) + row + dy) * kTileW + col);
+#pragma unroll
+        for (int cg = 0; cg < 4; ++cg)
+          acc[cg][tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[cg], bv, acc[cg][tap], 0, 0, 0);
+      }
+    }
+  }
+  // acc[cg][tap][r] = dW[co = 16 cg + 4 g + r][tap][ci = 16 wave + n]
+  float* out = part + (int64_t)blockIdx.x * kMidStride;
+#pragma unroll
+  for (int cg = 0; cg < 4; ++cg)
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[((16 * cg + 4 * g + r) * 9 + tap) * 64 + 16 * wave + n] = acc[cg][tap][r];
+  if (threadIdx.x < 64) out[kMidW + threadIdx.x] = bacc;
+}
+
+// out[i] = sum over w < nparts of part[w * stride + i] (fixed order).
+__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int nparts, int64_t stride,
+                                                  int64_t len, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= len) return;
+  float s = 0.f;
+  for (int w = 0; w < nparts; ++w) s += part[(int64_t)w * stride + i];
+  out[i] = s;
+}
+
+// Adam with bias correction: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                             const float* __restrict__ grad, int64_t n, float lr, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float g = grad[i];
+  const float mi = 0.9f * m[i] + 0.1f * g;
+  const float vi = 0.999f * v[i] + 0.001f * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
 }  // namespace abcs

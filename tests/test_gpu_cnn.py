@@ -79,3 +79,91 @@ def test_cnn_zero_last_layer_is_identity():
     im = synth.synth_image(102, 32, 32).astype(np.float64)
     got = _gpu_forward([im], [30.0], ocnn.pack(layers))[0]
     assert np.array_equal(got, im.astype(np.float32))
+
+
+def _train_setup(images, sigmas, targets, blob):
+    import torch
+    import paper_2001_09632_amd as g
+    dev = device()
+    plan = g.Plan([dict(height=im.shape[0], width=im.shape[1], block=16, subrate=0.25, method="zz",
+                        pixel_offset=0) for im in images])
+
+    def put(arrs):
+        t = torch.zeros(plan.pixels, dtype=torch.float32, device=dev)
+        for i, a in enumerate(arrs):
+            o = plan.images[i]["out_offset"]
+            t[o:o + a.size] = torch.from_numpy(a.astype(np.float32).reshape(-1)).to(dev)
+        return t
+
+    st = dict(plan=plan, x=put(images), t=put(targets),
+              sig=torch.tensor(sigmas, dtype=torch.float32, device=dev),
+              prm=torch.from_numpy(blob.astype(np.float32)).to(dev),
+              m=torch.zeros(len(blob), dtype=torch.float32, device=dev),
+              v=torch.zeros(len(blob), dtype=torch.float32, device=dev),
+              loss=torch.zeros(1, dtype=torch.float32, device=dev),
+              grad=torch.zeros(len(blob), dtype=torch.float32, device=dev),
+              ws=torch.empty(g.cnn_train_workspace_bytes(plan), dtype=torch.uint8, device=dev))
+    return st
+
+
+def _step(st, step, lr, grad=True):
+    import torch
+    import paper_2001_09632_amd as g
+    g.cnn_train_step(st["plan"], st["prm"], st["m"], st["v"], step, lr, st["x"], st["sig"], st["t"], st["loss"],
+                     st["grad"] if grad else None, workspace=st["ws"])
+    torch.cuda.synchronize()
+    return float(st["loss"].cpu()[0])
+
+
+def test_cnn_gradients_match_oracle():
+    blob = _blob(13)
+    rng = np.random.default_rng(14)
+    imgs = [synth.synth_image(110, 32, 32).astype(np.float64), synth.synth_image(111, 16, 48).astype(np.float64)]
+    tgts = [np.clip(im + rng.normal(0, 15, im.shape), 0, 255) for im in imgs]
+    sig = [20.0, 60.0]
+    st = _train_setup(imgs, sig, tgts, blob)
+    loss = _step(st, 1, 0.0)
+    g_gpu = st["grad"].cpu().numpy().astype(np.float64)
+    rb = ocnn.pack([(bf16_round(w), b) for w, b in ocnn.unpack(blob)])
+    # the oracle's loss is a mean over all pixels of the batch: stack the two
+    # images' terms with their pixel counts
+    n = [im.size for im in imgs]
+    l_ref, g_ref = 0.0, np.zeros_like(blob)
+    for i in range(2):
+        li, gi = ocnn.loss_and_grad(rb, imgs[i][None], [sig[i]], tgts[i][None])
+        l_ref += li * n[i] / sum(n)
+        g_ref += gi * n[i] / sum(n)
+    assert abs(loss - l_ref) < 2e-2 * l_ref, (loss, l_ref)
+    sizes = [int(np.prod(w)) + b[0] for w, b in ocnn.layer_shapes()]
+    o = 0
+    for li_, sz in enumerate(sizes):
+        a, b = g_gpu[o:o + sz], g_ref[o:o + sz]
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
+        rel = float(np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30))
+        assert cos > 0.995 and rel < 0.1, (li_, cos, rel)
+        o += sz
+
+
+def test_cnn_adam_update_rule():
+    blob = _blob(15)
+    rng = np.random.default_rng(16)
+    im = synth.synth_image(112, 32, 32).astype(np.float64)
+    st = _train_setup([im], [30.0], [np.clip(im + rng.normal(0, 10, im.shape), 0, 255)], blob)
+    p0 = st["prm"].cpu().numpy().astype(np.float64)
+    _step(st, 1, 1e-3)
+    g = st["grad"].cpu().numpy().astype(np.float64)
+    p1 = st["prm"].cpu().numpy().astype(np.float64)
+    exp, _, _ = ocnn.adam_step(p0, np.zeros_like(p0), np.zeros_like(p0), g, 1, 1e-3)
+    assert np.max(np.abs(p1 - exp)) < 1e-6
+
+
+def test_cnn_training_reduces_loss():
+    blob = _blob(17)
+    rng = np.random.default_rng(18)
+    clean = [synth.synth_image(120 + i, 32, 32).astype(np.float64) for i in range(4)]
+    noisy = [c + rng.normal(0, 20, c.shape) for c in clean]
+    st = _train_setup(noisy, [20.0] * 4, clean, blob)
+    l0 = _step(st, 1, 1e-3, grad=False)
+    for t in range(2, 81):
+        last = _step(st, t, 1e-3, grad=False)
+    assert last < 0.7 * l0, (l0, last)
