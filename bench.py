@@ -63,6 +63,92 @@ def algorithmic_bytes(plan, kind):
     raise ValueError(kind)
 
 
+IDA_SEEDS = list(range(2000, 2032))
+IDA_SIZES = [256] * 16 + [512] * 16
+IDA_ITERS = 30
+
+
+def ida_workload():
+    """16 x 256^2 + 16 x 512^2 synthetic images, C_R ~ U(0.1, 0.3) drawn from
+    stream seed 3, AL-DCT-DD on even and AL-DCT-BBV on odd images, B = 16."""
+    import numpy as np
+    import synth
+    crs = np.random.default_rng(3).uniform(0.1, 0.3, size=len(IDA_SEEDS))
+    imgs = [synth.synth_image(s, n, n) for s, n in zip(IDA_SEEDS, IDA_SIZES)]
+    methods = ["dd" if i % 2 == 0 else "bbv" for i in range(len(imgs))]
+    return imgs, crs, methods
+
+
+def ida_section(dev, weights_path):
+    """Plain IDA (BM3D, 30 iterations, D_F = 2) against learned IDA (CNN) on
+    one mixed batch: images/s and PSNR/SSIM against the ground truth; the
+    learned loop runs the fewest of 5, 10, ..., 30 iterations that reaches the
+    plain loop's PSNR minus 0.1 dB."""
+    import numpy as np
+    import torch
+    import paper_2001_09632_amd as g
+    from paper_2001_09632_amd import quality
+    from paper_2001_09632_amd.train import encode_batch, load_params
+    imgs, crs, methods = ida_workload()
+    plan, y, k, off = encode_batch(dev, imgs, crs, methods)
+    n = len(imgs)
+
+    def scores(x):
+        h = x.cpu().numpy()
+        ps, ss = [], []
+        for i, im in enumerate(imgs):
+            d = plan.images[i]
+            est = h[d["out_offset"]:d["out_offset"] + im.size].reshape(im.shape)
+            ps.append(quality.psnr(est, im))
+            ss.append(quality.ssim(est, im))
+        return float(np.mean(ps)), float(np.mean(ss))
+
+    def timed(iters, den, params=None):
+        ws = torch.empty(g.ida_workspace_bytes(plan, den), dtype=torch.uint8, device=dev)
+        x = torch.empty(plan.pixels, dtype=torch.float32, device=dev)
+        g.ida_refine(plan, y, k, off, x, iters, 2.0, den, params=params, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.ida_refine(plan, y, k, off, x, iters, 2.0, den, params=params, workspace=ws)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, x
+
+    io = torch.empty(plan.pixels, dtype=torch.float32, device=dev)
+    g.reconstruct(plan, y, k, off, io)
+    io_p, io_s = scores(io)
+    tp, xp = timed(IDA_ITERS, "bm3d")
+    pp, sp = scores(xp)
+    rec = {"workload": "16x256^2 + 16x512^2 synthetic images, C_R ~ U(0.1,0.3), B=16, D_F=2",
+           "images": n, "io": {"psnr": round(io_p, 3), "ssim": round(io_s, 4)},
+           "plain": {"denoiser": "bm3d", "iters": IDA_ITERS, "images_per_s": round(n / tp, 2),
+                     "ms_per_batch": round(tp * 1e3, 2), "psnr": round(pp, 3), "ssim": round(sp, 4)}}
+    if not os.path.exists(weights_path):
+        rec["learned"] = None
+        rec["note"] = f"no CNN weights at {weights_path}"
+        return rec
+    prm = torch.from_numpy(load_params(weights_path)).to(dev)
+    trail = {}
+    chosen = None
+    for it in (5, 10, 15, 20, 25, 30):
+        tl, xl = timed(it, "cnn", prm)
+        pl, sl = scores(xl)
+        trail[it] = round(pl, 3)
+        if chosen is None and pl >= pp - 0.1:
+            chosen = (it, tl, pl, sl)
+    matched = chosen is not None
+    if not matched:
+        tl, xl = timed(IDA_ITERS, "cnn", prm)
+        pl, sl = scores(xl)
+        chosen = (IDA_ITERS, tl, pl, sl)
+    it, tl, pl, sl = chosen
+    rec["learned"] = {"denoiser": "cnn", "iters": it, "images_per_s": round(n / tl, 2),
+                      "ms_per_batch": round(tl * 1e3, 2), "psnr": round(pl, 3), "ssim": round(sl, 4),
+                      "psnr_by_iters": trail}
+    rec["matched_psnr"] = matched
+    rec["learned_over_plain_images_per_s"] = round(tp / tl, 2)
+    return rec
+
+
 def cpu_baseline(images, n_images, deadline_s=30.0):
     """The FP64 oracle (budget + sensing + decoding) on the first n_images of
     the batch at every (estimator, subrate) pair; single-threaded numpy."""
@@ -92,6 +178,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-images", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ida", action="store_true")
+    ap.add_argument("--cnn-weights", default=os.path.join(ROOT, "paper_2001_09632_amd", "weights", "ida_cnn.npy"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batch would shard by "
@@ -154,6 +242,11 @@ def main():
                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
     per_kernel_ms = dict(budget=round(ms_budget, 4), sense=round(ms_sense, 4), reconstruct=round(ms_recon, 4))
 
+    ida = None
+    if not args.no_ida:
+        log("ida")
+        ida = ida_section(dev, args.cnn_weights)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -179,6 +272,7 @@ def main():
         "per_kernel_ms": per_kernel_ms,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "ida": ida,
     }
     print(json.dumps(rec), flush=True)
 

@@ -167,6 +167,16 @@ int abcs_reconstruct(const abcs_plan* plan, const float* d_y, const int32_t* d_k
  * Errors: EINVAL, EDOMAIN (D_F < 1 or NaN), EUNSUPPORTED (denoiser not
  * built), ENOSPACE (workspace too small), EHIP. */
 size_t ida_workspace_bytes(const abcs_plan* plan, int denoiser);
+/* Resumable form: runs iterations t = t_begin .. t_end-1 of the same loop.
+ * t_begin = 0 starts from x^0 = 0 and z^{-1} = 0; t_begin > 0 continues from
+ * the x^{t_begin} in d_x and the residual state left in d_ws by the call that
+ * ran iteration t_begin - 1 (same plan, y, k, offsets, damping, denoiser).
+ * d_sigma_trace (nullable) receives (t_end - t_begin) * n values; d_v_last
+ * (nullable, float[pixels]) receives v^{t_end-1} = x + A* z, the denoiser's
+ * input of the last iteration.  ida_refine(iters) = ida_iterate(0, iters). */
+int ida_iterate(const abcs_plan* plan, const float* d_y, const int32_t* d_k, const int64_t* d_offsets,
+                int t_begin, int t_end, double damping, int denoiser, const void* d_params, float* d_x,
+                float* d_sigma_trace, float* d_v_last, void* d_ws, size_t ws_bytes, void* stream);
 int ida_refine(const abcs_plan* plan, const float* d_y, const int32_t* d_k, const int64_t* d_offsets,
                int iters, double damping, int denoiser, const void* d_params, float* d_x,
                float* d_sigma_trace, void* d_ws, size_t ws_bytes, void* stream);
@@ -181,6 +191,8 @@ int ida_refine(const abcs_plan* plan, const float* d_y, const int32_t* d_k, cons
  * search, groups of at most 16 / 32 (thresholds 2500 / 400 on ||P-Q||^2/64),
  * 8x8 DCT + Haar 3D transform, hard threshold 2.7 sigma, Wiener second stage,
  * Kaiser (beta 2) aggregation; results are bit-identical from run to run.
+ * The CNN (parameters in d_params, see abcs_cnn_param_count) falls back to
+ * BM3D for every image whose network output holds a non-finite value.
  * d_ws: workspace of abcs_denoise_workspace_bytes(plan, denoiser) bytes,
  * 256-byte aligned (NULL allowed when that is 0). */
 size_t abcs_denoise_workspace_bytes(const abcs_plan* plan, int denoiser);

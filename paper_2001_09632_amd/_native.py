@@ -11,7 +11,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EDOMAIN", -3: "EUNSUPPORTED", -4: "E
 EXPORTS = [
     "abcs_plan_create", "abcs_plan_destroy", "abcs_plan_totals", "abcs_plan_image",
     "abcs_budget", "abcs_sense", "abcs_reconstruct", "abcs_dct_basis", "abcs_last_error",
-    "ida_workspace_bytes", "ida_refine", "abcs_denoise_workspace_bytes", "abcs_denoise",
+    "ida_workspace_bytes", "ida_refine", "ida_iterate", "abcs_denoise_workspace_bytes", "abcs_denoise",
     "abcs_cnn_param_count", "abcs_cnn_train_workspace_bytes", "abcs_cnn_train_step",
 ]
 
@@ -64,6 +64,7 @@ def lib():
     L.ida_workspace_bytes.argtypes = [vp, i32]
     L.ida_workspace_bytes.restype = sz
     L.ida_refine.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp, sz, vp]
+    L.ida_iterate.argtypes = [vp, vp, vp, vp, i32, i32, ctypes.c_double, i32, vp, vp, vp, vp, vp, sz, vp]
     L.abcs_denoise_workspace_bytes.argtypes = [vp, i32]
     L.abcs_denoise_workspace_bytes.restype = sz
     L.abcs_denoise.argtypes = [vp, i32, vp, vp, vp, vp, vp, sz, vp]

@@ -110,6 +110,16 @@ def ida_refine(plan, y, k, offsets, x, iters, damping=2.0, denoiser="identity", 
                            _stream(stream)))
 
 
+def ida_iterate(plan, y, k, offsets, x, t_begin, t_end, damping=2.0, denoiser="identity", params=None,
+                sigma_trace=None, v_last=None, workspace=None, stream=None):
+    """ida_iterate: resumable IDA iterations t_begin .. t_end-1."""
+    d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().ida_iterate(plan.handle, _ptr(y), _ptr(k), _ptr(offsets), int(t_begin), int(t_end),
+                            float(damping), d, _ptr(params), _ptr(x), _ptr(sigma_trace), _ptr(v_last),
+                            _ptr(workspace), ws_bytes, _stream(stream)))
+
+
 def denoise_workspace_bytes(plan, denoiser):
     d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
     return int(lib().abcs_denoise_workspace_bytes(plan.handle, d))

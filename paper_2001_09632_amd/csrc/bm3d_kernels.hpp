@@ -372,7 +372,8 @@ __global__ __launch_bounds__(256) void k_bm3d_filter(const ImgDev* __restrict__ 
   }
 }
 
-// out = num / den for images with sigma > 0, out = in otherwise.
+// out = num / den for images with sigma > 0, out = in for sigma <= 0; images
+// whose sigma is NaN are skipped by every BM3D kernel.
 __global__ __launch_bounds__(256) void k_bm3d_finish(const ImgDev* __restrict__ imgs, int n_imgs,
                                                     const float* __restrict__ sigma,
                                                     const unsigned long long* __restrict__ num,
@@ -382,11 +383,12 @@ __global__ __launch_bounds__(256) void k_bm3d_finish(const ImgDev* __restrict__ 
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= pixels) return;
   const int im = pix_img[i >> 8];
-  if (sigma[im] > 0.f) {
+  const float sg = sigma[im];
+  if (sg > 0.f) {
     out[i] = (float)((double)(long long)num[i] / (double)(long long)den[i]);
-  } else {
+  } else if (!__builtin_isnan(sg)) {
     out[i] = in[i];
-  }
+  }  // NaN: the image is not denoised by this call and its output is left alone
 }
 
 __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* __restrict__ p, int64_t n) {

@@ -249,6 +249,29 @@ __global__ __launch_bounds__(256) void k_cnn_last(const ImgDev* __restrict__ img
   out[p] = v[p] - 255.f * f;
 }
 
+// Fallback selection: sig_fb[i] = sigma[i] when image i's network output holds
+// a non-finite value, NaN otherwise (NaN makes the BM3D kernels skip the
+// image).  bad[] must be zero on entry.
+__global__ __launch_bounds__(256) void k_cnn_check(const int32_t* __restrict__ pix_img, int64_t pixels,
+                                                  const float* __restrict__ out, int32_t* __restrict__ bad) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= pixels) return;
+  if (!__builtin_isfinite(out[p])) atomicOr(&bad[pix_img[p >> 8]], 1);
+}
+
+__global__ void k_cnn_fallback_sigma(const int32_t* __restrict__ bad, const float* __restrict__ sigma, int n,
+                                     float* __restrict__ sig_fb, int32_t* __restrict__ bad_reset) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  sig_fb[i] = bad[i] ? sigma[i] : __builtin_nanf("");
+  (void)bad_reset;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Training: loss, gradients, Adam.  The loss is the mean over the batch's
 // pixels of ((D(v) - target) / 255)^2; df = dL/df = -2 (D(v) - target) / (255 n)

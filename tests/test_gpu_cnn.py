@@ -167,3 +167,24 @@ def test_cnn_training_reduces_loss():
     for t in range(2, 81):
         last = _step(st, t, 1e-3, grad=False)
     assert last < 0.7 * l0, (l0, last)
+
+
+def test_cnn_falls_back_to_bm3d_on_non_finite_output():
+    import torch
+    import paper_2001_09632_amd as g
+    dev = device()
+    blob = _blob(19)
+    blob[-1] = np.nan                       # last bias: every output NaN
+    im = synth.synth_image(130, 48, 64).astype(np.float32)
+    plan = g.Plan([dict(height=48, width=64, block=16, subrate=0.25, method="zz", pixel_offset=0)])
+    xin = torch.from_numpy(im.reshape(-1)).to(dev)
+    sig = torch.tensor([20.0], dtype=torch.float32, device=dev)
+    out_c = torch.empty_like(xin)
+    out_b = torch.empty_like(xin)
+    ws = torch.empty(g.denoise_workspace_bytes(plan, "cnn"), dtype=torch.uint8, device=dev)
+    g.denoise(plan, xin, sig, out_c, "cnn", params=torch.from_numpy(blob.astype(np.float32)).to(dev),
+              workspace=ws)
+    ws2 = torch.empty(g.denoise_workspace_bytes(plan, "bm3d"), dtype=torch.uint8, device=dev)
+    g.denoise(plan, xin, sig, out_b, "bm3d", workspace=ws2)
+    torch.cuda.synchronize()
+    assert torch.equal(out_c, out_b)
