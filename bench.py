@@ -63,6 +63,39 @@ def algorithmic_bytes(plan, kind):
     raise ValueError(kind)
 
 
+# HBM traffic of a kernel on this workload: rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads for
+# a plain device copy of 1 GiB (`bench.py --copy-probe 1024`).  A reading holds
+# only for the kernel source it was taken on, so it is keyed by the SHA-256 of
+# the files that define the kernel; after any change the figure is null until
+# the counters are taken again.
+COPY_KIB = 1048576.0
+TRAFFIC = {
+    "reconstruct": dict(
+        sources=("common.hpp", "transform16.hpp", "sense_kernels.hpp"),
+        sha256="5805031d135f45270c4b445348391141606c9ff86da5e8d802a242e46c735310",
+        fetch_kib=98434.5625, write_kib=655360.0,
+        copy_fetch_kib=524301.25, copy_write_kib=1048576.0),
+}
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch from the counter readings above, or None."""
+    import hashlib
+    t = TRAFFIC.get(kind)
+    if t is None:
+        return None
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, "paper_2001_09632_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t["sha256"]:
+        return None
+    fetch = t["fetch_kib"] * COPY_KIB / t["copy_fetch_kib"]
+    write = t["write_kib"] * COPY_KIB / t["copy_write_kib"]
+    return int(round((fetch + write) * 1024))
+
+
 IDA_SEEDS = list(range(2000, 2032))
 IDA_SIZES = [256] * 16 + [512] * 16
 IDA_ITERS = 30
@@ -180,6 +213,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ida", action="store_true")
     ap.add_argument("--cnn-weights", default=os.path.join(ROOT, "paper_2001_09632_amd", "weights", "ida_cnn.npy"))
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only run a device-to-device copy of this many MiB (5 times) and exit; "
+                         "its FETCH_SIZE / WRITE_SIZE readings calibrate the traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batch would shard by "
@@ -193,6 +229,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * (1 << 20)) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 5}))
+        return
     log("generating images")
     images = make_images()
     px = torch.from_numpy(images.reshape(-1)).to(dev)
@@ -239,7 +284,8 @@ def main():
     dom = max(kernels, key=kernels.get)
     ach = algorithmic_bytes(plan, dom) / (kernels[dom] * 1e-3) / 1e9
     roofline = dict(bound="hbm", kernel=dom, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=measured_traffic(dom),
+                    algorithmic_bytes=algorithmic_bytes(plan, dom))
     per_kernel_ms = dict(budget=round(ms_budget, 4), sense=round(ms_sense, 4), reconstruct=round(ms_recon, 4))
 
     ida = None
