@@ -70,15 +70,21 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
 }
 
 // out = D^T C D per block with C zero beyond the block's k_i zigzag entries.
-// A block's k_i coefficients arrive with unit-stride loads (slots past k_i get
-// out-of-range offsets and read 0, the zero fill), go to LDS in zigzag order
-// and are gathered from there in the transform's operand layout.  All loads of
-// a tile are issued before any store.  Blocks are stored in pairs: lanes n < 8
-// of each 16-lane row hold rows of block b and lanes n >= 8 rows of block b + 1
-// (a DPP row rotation), so every store writes 8 rows x 128 bytes.
+// Lane l loads coefficients 4l .. 4l+3 of a block with one 16-byte load
+// (lanes wholly past k_i get an out-of-range offset and read nothing; the
+// slots past k_i in the last partial quad are zeroed in registers), the block
+// goes to LDS in zigzag order and is gathered from there in the transform's
+// operand layout.  All loads of a tile are issued before any store.  Blocks
+// are stored in pairs: lanes n < 8 of each 16-lane row hold rows of block b
+// and lanes n >= 8 rows of block b + 1 (a DPP row rotation), so every store
+// writes 8 rows x 128 bytes.  The decoded image is not read again by this
+// kernel, so the stores are non-temporal (streamed past the caches).
 __device__ __forceinline__ float row_ror8(float v) {
   return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), 0x128, 0xf, 0xf, false));
 }
+
+// Cache policy bits of a buffer store: non-temporal.
+constexpr int kStoreNT = 2;
 
 __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* __restrict__ imgs,
                                                                 const Tile* __restrict__ tiles, int ntiles,
@@ -86,6 +92,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
                                                                 const int32_t* __restrict__ k_all,
                                                                 const int64_t* __restrict__ off_all,
                                                                 float* __restrict__ out) {
+  typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
   __shared__ WaveLds lds[kWavesPerGroup][2];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
@@ -96,17 +103,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
   TileIO io;
   tile_io_init(io, im, tl, nullptr, y, k_all, off_all, L);
   const int lane = threadIdx.x & 63;
-  float v[kTileBlocks][4];
+  u32x4 v[kTileBlocks];
 #pragma unroll
   for (int b = 0; b < kTileBlocks; ++b) {
     const int kk = __builtin_amdgcn_readlane(io.k, b);
     const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(io.rel_lo, b);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int z = lane + 64 * q;
-      const uint32_t voff = z < kk ? rel4 + 4u * (uint32_t)z : 0xffffffffu;
-      v[b][q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(io.y, voff, 0, 0));
-    }
+    const uint32_t voff = 4 * lane < kk ? rel4 + 16u * (uint32_t)lane : 0xffffffffu;
+    v[b] = __builtin_amdgcn_raw_buffer_load_b128(io.y, voff, 0, 0);
   }
   const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + tl.out_base, 4 * (15 * im.Wc + 16 * tl.count));
   const bool lo = L.n < 8;
@@ -117,11 +120,17 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
   float* buf1 = lds[wave_in_group()][1].c;
 #pragma unroll
   for (int b = 0; b < kTileBlocks; b += 2) {
+    // coefficients of this lane's quad that lie past the block's k
+    const int ka = __builtin_amdgcn_readlane(io.k, b) - 4 * lane;
+    const int kb = __builtin_amdgcn_readlane(io.k, b + 1) - 4 * lane;
+    u32x4 va = v[b], vb = v[b + 1];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      buf0[lane + 64 * q] = v[b][q];
-      buf1[lane + 64 * q] = v[b + 1][q];
+    for (int j = 0; j < 4; ++j) {
+      va[j] = j < ka ? va[j] : 0u;
+      vb[j] = j < kb ? vb[j] : 0u;
     }
+    *(u32x4*)&buf0[4 * lane] = va;
+    *(u32x4*)&buf1[4 * lane] = vb;
     wave_lds_sync();
     float e0[4], e1[4];
 #pragma unroll
@@ -145,9 +154,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
     const bool keep = lo ? (b < tl.count) : (b + 1 < tl.count);
     const uint32_t v1 = keep ? o1 + 64u * b : 0xffffffffu;
     const uint32_t v2 = keep ? o2 + 64u * b : 0xffffffffu;
-    typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, S1), ro, v1, 0, 0);
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, S2), ro, v2, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, S1), ro, v1, 0, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, S2), ro, v2, 0, kStoreNT);
   }
 }
 
