@@ -70,13 +70,35 @@ __global__ __launch_bounds__(kGroupThreads) void k_bbv_stats(const ImgDev* __res
 // roundoff.
 // ---------------------------------------------------------------------------
 constexpr float kDDGuard = 0.02f;
+// Undecided coefficients are queued per wave and settled in float64 in
+// batches of 64.  A block adds at most m1 <= 128 (C_F >= 1), so the queue is
+// flushed before a block whenever fewer than 128 slots are free.
+constexpr int kDDListCap = 256;
+
+// Settles queued coefficients: lane j of each batch recomputes entry j in
+// float64 from the staged pixels and counts it for its block if |c| > T.
+__device__ __forceinline__ void dd_flush(const uint16_t* list, int n, const uint32_t* st, const double* sD, int T,
+                                         int32_t* ucnt) {
+  const int lane = threadIdx.x & 63;
+  wave_lds_sync();
+  for (int base = 0; base < n; base += 64) {
+    if (base + lane < n) {
+      const int e = list[base + lane];
+      const int b = e >> 8;
+      if (fabs(dct16_coef_f64(st + 4 * b, sD, (e >> 4) & 15, e & 15)) > (double)T) atomicAdd(&ucnt[b], 1);
+    }
+  }
+  wave_lds_sync();
+}
 
 __global__ __launch_bounds__(kGroupThreads) void k_dd_stats(const ImgDev* __restrict__ imgs,
                                                            const Tile* __restrict__ tiles, int ntiles,
                                                            const uint8_t* __restrict__ px,
                                                            int32_t* __restrict__ stat) {
   __shared__ double sD[256];
-  __shared__ uint32_t sblk[kWavesPerGroup][64];
+  __shared__ PxStage stage[kWavesPerGroup];
+  __shared__ uint16_t ulist[kWavesPerGroup][kDDListCap];
+  __shared__ int32_t ucount[kWavesPerGroup][kTileBlocks];
   sD[threadIdx.x] = c_D16d[threadIdx.x];
   __syncthreads();
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
@@ -86,47 +108,49 @@ __global__ __launch_bounds__(kGroupThreads) void k_dd_stats(const ImgDev* __rest
   Lane16 L;
   lane16_init(L);
   const int lane = threadIdx.x & 63;
-  uint32_t* words = sblk[wave_in_group()];
   const float T = (float)im.T;
-  const __amdgpu_buffer_rsrc_t rpx = make_rsrc(px + tl.px_base, 15 * im.pitch + 16 * tl.count);
-  const int px_lane = L.n * im.pitch + 4 * L.g;
-
-  uint32_t pw[kTileBlocks];
-#pragma unroll
-  for (int b = 0; b < kTileBlocks; ++b) pw[b] = __builtin_amdgcn_raw_buffer_load_b32(rpx, px_lane + 16 * b, 0, 0);
-  int32_t my_stat = 0;  // lane b keeps block b's count
-#pragma unroll
+  const int m1 = im.m1 < 128 ? im.m1 : 128;
+  TileIO io;
+  io.px = make_rsrc(px + tl.px_base, 15 * im.pitch + 16 * tl.count);
+  uint32_t* st = stage[wave_in_group()].w;
+  uint16_t* list = ulist[wave_in_group()];
+  int32_t* ucnt = ucount[wave_in_group()];
+  if (lane < kTileBlocks) ucnt[lane] = 0;
+  stage_tile_px(io, im.pitch, tl.count, st);
+  wave_lds_sync();
+  int32_t my_stat = 0;  // lane b keeps block b's count of coefficients decided in float32
+  int nlist = 0;        // wave-uniform length of the queue
+#pragma unroll 2
   for (int b = 0; b < kTileBlocks; ++b) {
-    {
-      float a[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) a[c] = (float)((pw[b] >> (8 * c)) & 0xffu);
-      const f32x4 C = dct16_fwd(a, L);
-      bool above[4], unsure[4];
-      bool any_unsure = false;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float av = fabsf(C[r]);
-        const bool in = L.zr[r] < im.m1;
-        above[r] = in && (av > T + kDDGuard);
-        unsure[r] = in && !above[r] && (av >= T - kDDGuard);
-        any_unsure |= unsure[r];
-      }
-      if (__ballot(any_unsure) != 0) {
-        words[lane] = pw[b];
-        wave_lds_sync();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (unsure[r]) above[r] = fabs(dct16_coef_f64(words, sD, 4 * L.g + r, L.n)) > (double)im.T;
-        }
-        wave_lds_sync();
-      }
-      int cnt = 0;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) cnt += __popcll(__ballot(above[r]));
-      if (lane == b) my_stat = cnt;
+    if (nlist > kDDListCap - 128) {
+      dd_flush(list, nlist, st, sD, im.T, ucnt);
+      nlist = 0;
     }
+    const uint32_t pw = staged_px(st, b, L);
+    float a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = (float)((pw >> (8 * c)) & 0xffu);
+    const f32x4 C = dct16_fwd(a, L);
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float av = fabsf(C[r]);
+      const bool in = L.zr[r] < m1;
+      const bool above = in && (av > T + kDDGuard);
+      const bool unsure = in && !above && (av >= T - kDDGuard);
+      cnt += __popcll(__ballot(above));
+      const uint64_t um = __ballot(unsure);
+      if (um != 0) {
+        const int pos = nlist + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(um >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)um, 0u));
+        if (unsure) list[pos] = (uint16_t)((b << 8) | ((4 * L.g + r) << 4) | L.n);
+        nlist += __popcll(um);
+      }
+    }
+    if (lane == b) my_stat = cnt;
   }
+  if (nlist > 0) dd_flush(list, nlist, st, sD, im.T, ucnt);
+  if (lane < kTileBlocks) my_stat += ucnt[lane];
   if (lane < tl.count) stat[im.blk_off + tl.first + lane] = my_stat;
 }
 

@@ -33,6 +33,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
                                                           const int64_t* __restrict__ off_all,
                                                           float* __restrict__ y) {
   __shared__ WaveLds lds[kWavesPerGroup];
+  __shared__ PxStage stage[kWavesPerGroup];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
   const Tile tl = tiles[wave];
@@ -42,15 +43,16 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
   TileIO io;
   tile_io_init(io, im, tl, px, y, k_all, off_all, L);
   float* buf = lds[wave_in_group()].c;
+  uint32_t* st = stage[wave_in_group()].w;
   const int lane = threadIdx.x & 63;
-  uint32_t pw[kTileBlocks];
-#pragma unroll
-  for (int b = 0; b < kTileBlocks; ++b) pw[b] = tile_px(io, b);
+  stage_tile_px(io, im.pitch, tl.count, st);
+  wave_lds_sync();
 #pragma unroll
   for (int b = 0; b < kTileBlocks; ++b) {
+    const uint32_t pw = staged_px(st, b, L);
     float a[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a[c] = (float)((pw[b] >> (8 * c)) & 0xffu);
+    for (int c = 0; c < 4; ++c) a[c] = (float)((pw >> (8 * c)) & 0xffu);
     const f32x4 C = dct16_fwd(a, L);
 #pragma unroll
     for (int r = 0; r < 4; ++r) buf[L.zr[r]] = C[r];

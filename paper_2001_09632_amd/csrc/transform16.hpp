@@ -79,7 +79,6 @@ __device__ __forceinline__ f32x4 idct16_inv(const float e[4], const Lane16& L) {
 // tile's pixels, the image's part of y and the tile's output rows.
 struct TileIO {
   __amdgpu_buffer_rsrc_t px;   // uint8 pixels of the tile's 16 rows
-  int px_lane;                 // byte offset of the lane's 4 pixels in block 0
   __amdgpu_buffer_rsrc_t y;    // the image's coefficients in y
   int32_t k;                   // lane b < count: k of block b
   int32_t rel_lo;              // lane b < count: offsets[b] - meas_off (low 32 bits)
@@ -89,7 +88,6 @@ __device__ __forceinline__ void tile_io_init(TileIO& io, const ImgDev& im, const
                                              const float* y, const int32_t* k_all, const int64_t* off_all,
                                              const Lane16& L) {
   io.px = make_rsrc(px + tl.px_base, px ? 15 * im.pitch + 16 * tl.count : 0);
-  io.px_lane = L.n * im.pitch + 4 * L.g;
   io.y = make_rsrc(y + im.meas_off, y ? (int)(4 * im.n_meas) : 0);
   const int lane = threadIdx.x & 63;
   const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
@@ -98,9 +96,35 @@ __device__ __forceinline__ void tile_io_init(TileIO& io, const ImgDev& im, const
   io.rel_lo = (int32_t)(__builtin_amdgcn_raw_buffer_load_b32(ro, 8 * lane, 0, 0) - (uint32_t)im.meas_off);
 }
 
-// Lane's pixel word of block b of the tile (0 past the tile's end).
-__device__ __forceinline__ uint32_t tile_px(const TileIO& io, int b) {
-  return __builtin_amdgcn_raw_buffer_load_b32(io.px, io.px_lane + 16 * b, 0, 0);
+// Pixels of a tile staged in LDS.  The tile's 16 pixel rows (16 blocks x 16
+// bytes each) are read with row-contiguous 16-byte loads: lane l of load i
+// takes row 4i + l / 16, block l % 16, so each load covers four rows of 256
+// contiguous bytes (reading the transform's layout directly instead would
+// make every load touch 16 rows for 16 bytes each).  Rows are kPxRow bytes
+// apart in LDS; the 16-byte pad puts the 64 words that one transform-layout
+// read touches (rows n, words g of a block) in 64 different banks.  Blocks past
+// the tile's end read as zero.
+constexpr int kPxRow = 272;
+struct PxStage {
+  uint32_t w[16 * kPxRow / 4];
+};
+
+__device__ __forceinline__ void stage_tile_px(const TileIO& io, int pitch, int count, uint32_t* st) {
+  typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+  const int lane = threadIdx.x & 63;
+  const int bl = lane & 15, rr = lane >> 4;
+  const uint32_t past = bl < count ? 0u : 0xffffffffu;
+  u32x4 d[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    d[i] = __builtin_amdgcn_raw_buffer_load_b128(io.px, (uint32_t)((4 * i + rr) * pitch + 16 * bl) | past, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) *(u32x4*)&st[((4 * i + rr) * kPxRow + 16 * bl) / 4] = d[i];
+}
+
+// Lane's pixel word of block b from the stage: pixels (n, 4g .. 4g+3).
+__device__ __forceinline__ uint32_t staged_px(const uint32_t* st, int b, const Lane16& L) {
+  return st[(L.n * kPxRow + 16 * b + 4 * L.g) / 4];
 }
 
 // Byte offsets in y of the coefficients of zigzag ranks zr[c] of block b, or
@@ -137,20 +161,21 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
 // T[r] = sum_j X[r][j] D[v][j] (j ascending), C = sum_r D[u][r] T[r]
 // (r ascending), every product and sum rounded on its own.  Used to settle
 // DD threshold decisions that the float32 path cannot decide.  `words` is the
-// block staged in LDS in the transform's operand layout: word 16g + r holds
-// pixels (r, 4g .. 4g+3), one per byte; `D` is the float64 basis.  The 16 row
+// block in a pixel stage (PxStage, offset to the block): word r kPxRow / 4 + g
+// holds pixels (r, 4g .. 4g+3), one per byte; `D` is the float64 basis.  The 16 row
 // sums are independent and advance together, so the dependent chain is 16 + 16
 // additions long.
-__device__ __attribute__((noinline)) double dct16_coef_f64(const uint32_t* words, const double* D, int u, int v) {
+__device__ __forceinline__ double dct16_coef_f64(const uint32_t* words, const double* D, int u, int v) {
 #pragma clang fp contract(off)
   double t[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) t[r] = 0.0;
-#pragma unroll
+  // one column group at a time keeps 16 pixel words and 4 basis values live
+#pragma unroll 1
   for (int q = 0; q < 4; ++q) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const uint32_t w = words[q * 16 + r];
+      const uint32_t w = words[r * (kPxRow / 4) + q];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const double x = (double)((w >> (8 * c)) & 0xffu);

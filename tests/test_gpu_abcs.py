@@ -98,6 +98,52 @@ def test_degenerate_images():
         _check_image(run, j, imgs[i], 16, cr, m)
 
 
+def _tie_blocks(seed, n):
+    """n blocks whose coefficient C[8][0] is +-60 in exact arithmetic.
+
+    Basis row 8 is s(x) / 4 with s = +1, -1, -1, +1, ... (cos of odd multiples
+    of pi/4), so a block whose columns C of a random set of |R| columns hold a
+    on rows with s = +1 and a - d elsewhere has C[8][0] = |R| d / 2.  With
+    |R| d = 120 that is the DD threshold 60; the float64 value lands on, just
+    above or just below 60 depending on the rounding of the basis."""
+    s8 = np.sign(np.cos((2 * np.arange(16) + 1) * np.pi / 4))
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(n):
+        R, d = [(8, 15), (10, 12), (12, 10), (15, 8), (4, 30), (6, 20), (5, 24)][t % 7]
+        a = int(rng.integers(d, 256))
+        cols = rng.choice(16, R, replace=False)
+        blk = np.zeros((16, 16), np.uint8)
+        blk[:, cols] = np.where(s8 > 0, a, a - d)[:, None]
+        if rng.integers(0, 2):
+            blk = np.roll(blk, 2, 0)                      # flips the sign of row 8
+        out.append(blk)
+    return out
+
+
+def test_dd_many_exact_ties():
+    """256 blocks, each with C[8][0] = +-T exactly in real arithmetic: every
+    block sends coefficients into the float64 recheck, whose decisions (above,
+    equal or below T by a few ulps in the canonical order) must be the
+    oracle's."""
+    blocks = _tie_blocks(11, 256)
+    img = np.zeros((256, 256), np.uint8)
+    for i, blk in enumerate(blocks):
+        img[16 * (i // 16):16 * (i // 16) + 16, 16 * (i % 16):16 * (i % 16) + 16] = blk
+    D = orc.dct_matrix(16)
+    c80 = np.abs(orc.block_dct(np.stack(blocks).astype(np.float64), D)[:, 8, 0])
+    assert np.all(np.abs(c80 - 60) < 1e-9) and (c80 > 60).any() and (c80 <= 60).any()
+    crs = (0.29, 0.295)
+    for cr in crs:
+        assert orc.dd_threshold(256, 1 / cr) == 60
+        assert orc.budget_scalars(256, 256, 16, cr, orc.DD)["m1"] >= 37     # (8, 0) has zigzag rank 36
+    px, d = pack_images([img])
+    run = Run(px, [dict(d[0], block=16, subrate=cr, method="dd") for cr in crs]).budget().sense() \
+        .reconstruct().fetch()
+    for j, cr in enumerate(crs):
+        _check_image(run, j, img, 16, cr, orc.DD)
+
+
 def test_decoder_on_oracle_measurements():
     img = synth.synth_image(5, 256, 256)
     px, d = pack_images([img])
