@@ -181,6 +181,23 @@ int ida_refine(const abcs_plan* plan, const float* d_y, const int32_t* d_k, cons
                int iters, double damping, int denoiser, const void* d_params, float* d_x,
                float* d_sigma_trace, void* d_ws, size_t ws_bytes, void* stream);
 
+/* The IDA loop as a replayable HIP graph: ida_graph_create records the
+ * launches of ida_refine(plan, d_y, d_k, d_offsets, iters, damping, denoiser,
+ * d_params, d_x, d_sigma_trace, d_ws, ws_bytes) into one instantiated graph
+ * (stream capture; every node is a kernel), and each ida_graph_launch replays
+ * the whole T-iteration loop on `stream` with one call.  The buffers named at
+ * creation are the ones every replay reads and writes; the caller keeps them
+ * (and the plan) alive and unchanged in size until ida_graph_destroy.  A replay
+ * gives the same result as ida_refine with the same arguments.
+ * Errors: as ida_refine, plus EHIP when capture or instantiation fails (no
+ * graph is returned then). */
+typedef struct abcs_ida_graph abcs_ida_graph;
+int ida_graph_create(const abcs_plan* plan, const float* d_y, const int32_t* d_k, const int64_t* d_offsets,
+                     int iters, double damping, int denoiser, const void* d_params, float* d_x,
+                     float* d_sigma_trace, void* d_ws, size_t ws_bytes, abcs_ida_graph** out);
+int ida_graph_launch(abcs_ida_graph* graph, void* stream);
+void ida_graph_destroy(abcs_ida_graph* graph);
+
 /* Apply an IDA denoiser D_sigma to every image of a plan (the step
  * x^{t+1} = D_sigma(v^t) of ida_refine, exposed on its own).
  * d_in, d_out: float[pixels], each image H' x W' with row pitch W', 16-byte

@@ -110,6 +110,40 @@ def ida_refine(plan, y, k, offsets, x, iters, damping=2.0, denoiser="identity", 
                            _stream(stream)))
 
 
+class IdaGraph:
+    """ida_graph_create / ida_graph_launch / ida_graph_destroy: the whole
+    ida_refine loop recorded once as a HIP graph and replayed per launch().
+    The tensors passed here are the ones every replay uses; this object keeps
+    references to them (and to the plan) until close()."""
+
+    def __init__(self, plan, y, k, offsets, x, iters, damping=2.0, denoiser="identity", params=None,
+                 sigma_trace=None, workspace=None):
+        d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
+        ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+        self._keep = (plan, y, k, offsets, x, params, sigma_trace, workspace)
+        self._h = ctypes.c_void_p()
+        check(lib().ida_graph_create(plan.handle, _ptr(y), _ptr(k), _ptr(offsets), int(iters), float(damping), d,
+                                     _ptr(params), _ptr(x), _ptr(sigma_trace), _ptr(workspace), ws_bytes,
+                                     ctypes.byref(self._h)))
+
+    def launch(self, stream=None):
+        if not self._h:
+            raise RuntimeError("graph is closed")
+        check(lib().ida_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().ida_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def ida_iterate(plan, y, k, offsets, x, t_begin, t_end, damping=2.0, denoiser="identity", params=None,
                 sigma_trace=None, v_last=None, workspace=None, stream=None):
     """ida_iterate: resumable IDA iterations t_begin .. t_end-1."""

@@ -114,4 +114,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_ida_sigma(const ImgDev* __res
   }
 }
 
+// dst[i] = src[i], i < n (a kernel, so that captured graphs hold kernel nodes only).
+__global__ __launch_bounds__(256) void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 }  // namespace abcs
