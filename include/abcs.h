@@ -77,7 +77,7 @@ typedef struct abcs_image {
   int32_t width;         /* W, columns of the uncropped image                */
   int32_t row_pitch;     /* bytes between rows of the uint8 pixels; >= W,
                             multiple of 4                                    */
-  int32_t block;         /* B: 16 (8 and 32 are reserved, EUNSUPPORTED)      */
+  int32_t block;         /* B: 8, 16 or 32                                   */
   double subrate;        /* C_R in (0, 1]                                    */
   int32_t method;        /* abcs_method                                      */
   int32_t reserved;      /* must be 0                                        */
@@ -102,7 +102,9 @@ typedef struct abcs_plan abcs_plan; /* opaque */
  * that must be released with abcs_plan_destroy.
  * Errors: EINVAL (null pointer, n < 0, pitch/offset/alignment), EDOMAIN
  * (C_R outside (0,1], no whole block, M = 0, BBV with C_R > 0.5, BBV samples
- * exceeding M), EUNSUPPORTED (B != 16), EHIP. */
+ * exceeding M), EUNSUPPORTED (B not 8, 16 or 32), EHIP.  B = 16 runs on the
+ * matrix cores; B = 8 and 32 run on the vector ALUs (same results and error
+ * bars: budgets and index sets exact, DD statistics evaluated in float64). */
 int abcs_plan_create(const abcs_image* h_imgs, int n, abcs_plan** out);
 void abcs_plan_destroy(abcs_plan* plan);
 
@@ -165,7 +167,8 @@ int abcs_reconstruct(const abcs_plan* plan, const float* d_y, const int32_t* d_k
  * d_ws:          workspace of at least ida_workspace_bytes(plan, denoiser)
  *                bytes, 256-byte aligned; overwritten.
  * Errors: EINVAL, EDOMAIN (D_F < 1 or NaN), EUNSUPPORTED (denoiser not
- * built), ENOSPACE (workspace too small), EHIP. */
+ * built, or the CNN on a plan with an image whose W' is not a multiple of 16
+ * or H' of 8, possible with B = 8), ENOSPACE (workspace too small), EHIP. */
 size_t ida_workspace_bytes(const abcs_plan* plan, int denoiser);
 /* Resumable form: runs iterations t = t_begin .. t_end-1 of the same loop.
  * t_begin = 0 starts from x^0 = 0 and z^{-1} = 0; t_begin > 0 continues from

@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void k_bm3d_finish(const ImgDev* __restrict__ 
                                                     int64_t pixels, const int32_t* __restrict__ pix_img) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= pixels) return;
-  const int im = pix_img[i >> 8];
+  const int im = pix_img[i >> kPixChunkShift];
   const float sg = sigma[im];
   if (sg > 0.f) {
     out[i] = (float)((double)(long long)num[i] / (double)(long long)den[i]);

@@ -84,10 +84,10 @@ __global__ __launch_bounds__(256) void k_cnn_first(const ImgDev* __restrict__ im
   __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= pixels) return;
-  const ImgDev im = imgs[pix_img[p >> 8]];
+  const ImgDev im = imgs[pix_img[p >> kPixChunkShift]];
   const int64_t lp = p - im.out_off;
   const int y = (int)(lp / im.Wc), x = (int)(lp - (int64_t)y * im.Wc);
-  const float s = fminf(sigma[pix_img[p >> 8]], 255.f) * (1.f / 255.f);
+  const float s = fminf(sigma[pix_img[p >> kPixChunkShift]], 255.f) * (1.f / 255.f);
   float in0[9], in1[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void k_cnn_last(const ImgDev* __restrict__ img
   __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= pixels) return;
-  const ImgDev im = imgs[pix_img[p >> 8]];
+  const ImgDev im = imgs[pix_img[p >> kPixChunkShift]];
   const int64_t lp = p - im.out_off;
   const int y = (int)(lp / im.Wc), x = (int)(lp - (int64_t)y * im.Wc);
   float f = blob[kB8];
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void k_cnn_check(const int32_t* __restrict__ p
                                                   const float* __restrict__ out, int32_t* __restrict__ bad) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= pixels) return;
-  if (!__builtin_isfinite(out[p])) atomicOr(&bad[pix_img[p >> 8]], 1);
+  if (!__builtin_isfinite(out[p])) atomicOr(&bad[pix_img[p >> kPixChunkShift]], 1);
 }
 
 __global__ void k_cnn_fallback_sigma(const int32_t* __restrict__ bad, const float* __restrict__ sigma, int n,
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void k_cnn_last_bwd(const ImgDev* __restrict__
   __syncthreads();
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= pixels) return;
-  const ImgDev im = imgs[pix_img[q >> 8]];
+  const ImgDev im = imgs[pix_img[q >> kPixChunkShift]];
   const int64_t lq = q - im.out_off;
   const int y = (int)(lq / im.Wc), x = (int)(lq - (int64_t)y * im.Wc);
   float d[9];
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void k_cnn_last_wgrad(const ImgDev* __restrict
   const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(pixels, p0 + chunk);
   float acc[3] = {0.f, 0.f, 0.f};
   for (int64_t p = p0; p < p1; ++p) {
-    const ImgDev im = imgs[pix_img[p >> 8]];
+    const ImgDev im = imgs[pix_img[p >> kPixChunkShift]];
     const int64_t lp = p - im.out_off;
     const int y = (int)(lp / im.Wc), x = (int)(lp - (int64_t)y * im.Wc);
     const float dv = df[p];
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void k_cnn_first_wgrad(const ImgDev* __restric
   const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(pixels, p0 + chunk);
   float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
   for (int64_t p = p0; p < p1; ++p) {
-    const int ii = pix_img[p >> 8];
+    const int ii = pix_img[p >> kPixChunkShift];
     const ImgDev im = imgs[ii];
     const int64_t lp = p - im.out_off;
     const int y = (int)(lp / im.Wc), x = (int)(lp - (int64_t)y * im.Wc);

@@ -12,6 +12,10 @@ constexpr int kTileBlocks = 16;
 constexpr int kWavesPerGroup = 4;
 constexpr int kGroupThreads = 64 * kWavesPerGroup;
 
+// Per-pixel kernels find a pixel's image from a table with one entry per
+// 64 decoded pixels (every image holds a multiple of 64 pixels: B >= 8).
+constexpr int kPixChunkShift = 6;
+
 enum Mode : int32_t { kModeZZ = 0, kModeBBV = 1, kModeDD = 2 };
 
 // Per-image parameters, derived on the host from the descriptor (eqs 16-21,

@@ -1,0 +1,354 @@
+// Block transforms for B = 8 and B = 32 on the vector ALUs: phase-1 DD
+// statistic (in float64, in the fixed order of the definition), sensing,
+// masked inverse DCT and the IDA transform step.  A workgroup takes a tile of
+// up to 16 consecutive blocks of a block row; wavefront w handles blocks
+// w, w + 4, ... of it.  Each wavefront keeps its block in LDS (row pitch B + 1
+// floats, so that a row and a column are both conflict-free) and runs the
+// separable transform as two passes of B-term dot products, one output per
+// lane per step.  The basis and the zigzag rank table are staged in LDS once
+// per workgroup.
+#pragma once
+
+#include "common.hpp"
+#include "transform16.hpp"
+#include "bm3d_kernels.hpp"
+
+namespace abcs {
+
+// Orthonormal DCT-II bases D[u*B + j] of orders 8 (c_D8, shared with BM3D)
+// and 32 (float32 copies of the host-built float64 table and the float64
+// table itself), and zigzag ranks of coefficient (u, v) at u*B + v with their
+// inverse (rank -> u*B + v).
+__constant__ double c_D8d[64];
+__constant__ float c_D32[1024];
+__constant__ double c_D32d[1024];
+__constant__ uint16_t c_zzrank8[64];
+__constant__ uint16_t c_zzpos8[64];
+__constant__ uint16_t c_zzrank32[1024];
+__constant__ uint16_t c_zzpos32[1024];
+
+template <int B>
+struct GenTables;
+template <>
+struct GenTables<8> {
+  __device__ static const float* D() { return c_D8; }
+  __device__ static const double* Dd() { return c_D8d; }
+  __device__ static const uint16_t* rank() { return c_zzrank8; }
+  __device__ static const uint16_t* pos() { return c_zzpos8; }
+};
+template <>
+struct GenTables<32> {
+  __device__ static const float* D() { return c_D32; }
+  __device__ static const double* Dd() { return c_D32d; }
+  __device__ static const uint16_t* rank() { return c_zzrank32; }
+  __device__ static const uint16_t* pos() { return c_zzpos32; }
+};
+
+template <int B>
+struct GenShared {
+  static constexpr int P = B + 1;        // LDS row pitch (elements)
+  static constexpr int NN = B * B;       // coefficients per block
+  static constexpr int PER = NN / 64;    // outputs per lane per pass (1 or 16)
+  float D[B * P];                        // D[u][j] at u P + j
+  uint16_t rank[NN];                     // zigzag rank of (u, v) at u B + v
+  float a[kWavesPerGroup][B * P];        // per wave: block / first pass
+  float b[kWavesPerGroup][B * P];        // per wave: second pass / rank-ordered buffer
+};
+
+template <int B>
+__device__ __forceinline__ void gen_load_tables(GenShared<B>& sh) {
+  constexpr int P = B + 1;
+  for (int t = threadIdx.x; t < B * B; t += kGroupThreads) {
+    sh.D[(t / B) * P + t % B] = GenTables<B>::D()[t];
+    sh.rank[t] = GenTables<B>::rank()[t];
+  }
+}
+
+// Pixels of block bb of the tile into X[r][c] (float, pitch B + 1); 4 pixels
+// per 32-bit load (rows are 4-byte aligned: pitch and pixel_offset are
+// multiples of 4, block columns multiples of 8).
+template <int B>
+__device__ __forceinline__ void gen_load_pixels(const __amdgpu_buffer_rsrc_t& rp, int pitch, int bb, float* X) {
+  constexpr int P = B + 1, WPR = B / 4;
+  const int lane = threadIdx.x & 63;
+  for (int idx = lane; idx < B * WPR; idx += 64) {
+    const int r = idx / WPR, cw = idx - r * WPR;
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rp, r * pitch + B * bb + 4 * cw, 0, 0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) X[r * P + 4 * cw + c] = (float)((w >> (8 * c)) & 0xffu);
+  }
+}
+
+// Forward 2D DCT: X (in a) -> C[u][v] (in a), using b.  Operands and the
+// intermediate are float32, each B-term sum is accumulated in float64 (the
+// vector units run float64 fused multiply-adds at the float32 rate), so the
+// result is within a few float32 roundings of exact even at B = 32.
+template <int B>
+__device__ __forceinline__ void gen_fwd(const float* D, float* a, float* b) {
+  constexpr int P = B + 1;
+  const int lane = threadIdx.x & 63;
+  // T[x][v] = sum_j X[x][j] D[v][j]
+  for (int idx = lane; idx < B * B; idx += 64) {
+    const int x = idx / B, v = idx - x * B;
+    double s = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < B; ++j) s = fma((double)a[x * P + j], (double)D[v * P + j], s);
+    b[x * P + v] = (float)s;
+  }
+  wave_lds_sync();
+  // C[u][v] = sum_x D[u][x] T[x][v]
+  for (int idx = lane; idx < B * B; idx += 64) {
+    const int u = idx / B, v = idx - u * B;
+    double s = 0.0;
+#pragma unroll 8
+    for (int x = 0; x < B; ++x) s = fma((double)D[u * P + x], (double)b[x * P + v], s);
+    a[u * P + v] = (float)s;
+  }
+  wave_lds_sync();
+}
+
+// Inverse 2D DCT: C (in a) -> X[x][x'] (in a), using b; sums as in gen_fwd.
+template <int B>
+__device__ __forceinline__ void gen_inv(const float* D, float* a, float* b) {
+  constexpr int P = B + 1;
+  const int lane = threadIdx.x & 63;
+  // Q[u][x'] = sum_v C[u][v] D[v][x']
+  for (int idx = lane; idx < B * B; idx += 64) {
+    const int u = idx / B, xp = idx - u * B;
+    double s = 0.0;
+#pragma unroll 8
+    for (int v = 0; v < B; ++v) s = fma((double)a[u * P + v], (double)D[v * P + xp], s);
+    b[u * P + xp] = (float)s;
+  }
+  wave_lds_sync();
+  // X[x][x'] = sum_u D[u][x] Q[u][x']
+  for (int idx = lane; idx < B * B; idx += 64) {
+    const int x = idx / B, xp = idx - x * B;
+    double s = 0.0;
+#pragma unroll 8
+    for (int u = 0; u < B; ++u) s = fma((double)D[u * P + x], (double)b[u * P + xp], s);
+    a[x * P + xp] = (float)s;
+  }
+  wave_lds_sync();
+}
+
+// Block bb's coefficient count and its offset relative to the image's part of
+// y, clamped to that part (a corrupt k or offset cannot leave it).
+__device__ __forceinline__ void gen_block_range(const ImgDev& im, const int32_t* k_all, const int64_t* off_all,
+                                                int64_t blk, int nn, int& kk, int64_t& rel) {
+  const int64_t n = im.n_meas;
+  int k = k_all[blk];
+  int64_t r = off_all[blk] - im.meas_off;
+  if (r < 0 || r > n || k < 0) k = 0, r = 0;
+  if (k > nn) k = nn;
+  if (k > n - r) k = (int)(n - r);
+  kk = __builtin_amdgcn_readfirstlane(k);
+  rel = r;
+}
+
+// ---------------------------------------------------------------------------
+// DD n_i for B = 8 / 32 in float64: T[r][v] = sum_j X[r][j] D[v][j] (j
+// ascending), C[u][v] = sum_r D[u][r] T[r][v] (r ascending), every product
+// and sum rounded on its own; n_i = #{z < m1 : |C[zz(z)]| > T}.
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ __launch_bounds__(kGroupThreads) void k_gen_dd_stats(const ImgDev* __restrict__ imgs,
+                                                               const Tile* __restrict__ tiles, int ntiles,
+                                                               const uint8_t* __restrict__ px,
+                                                               int32_t* __restrict__ stat) {
+#pragma clang fp contract(off)
+  constexpr int P = B + 1;
+  __shared__ double sDd[B * B];
+  __shared__ uint16_t spos[B * B];
+  __shared__ float sX[kWavesPerGroup][B * P];
+  __shared__ double sT[kWavesPerGroup][B * P];
+  if ((int)blockIdx.x >= ntiles) return;
+  for (int t = threadIdx.x; t < B * B; t += kGroupThreads) {
+    sDd[t] = GenTables<B>::Dd()[t];
+    spos[t] = GenTables<B>::pos()[t];
+  }
+  __syncthreads();
+  const Tile tl = tiles[blockIdx.x];
+  const ImgDev im = imgs[tl.img];
+  const int w = wave_in_group(), lane = threadIdx.x & 63;
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, (B - 1) * im.pitch + B * tl.count);
+  float* X = sX[w];
+  double* T = sT[w];
+  const int m1 = im.m1 < B * B ? im.m1 : B * B;
+  const double thr = (double)im.T;
+  for (int bb = w; bb < tl.count; bb += kWavesPerGroup) {
+    gen_load_pixels<B>(rp, im.pitch, bb, X);
+    wave_lds_sync();
+    for (int idx = lane; idx < B * B; idx += 64) {
+      const int r = idx / B, v = idx - r * B;
+      double s = 0.0;
+      for (int j = 0; j < B; ++j) {
+        const double p = (double)X[r * P + j] * sDd[v * B + j];
+        s = s + p;
+      }
+      T[r * P + v] = s;
+    }
+    wave_lds_sync();
+    int cnt = 0;
+    for (int z = lane; z < m1; z += 64) {
+      const int uv = spos[z];
+      const int u = uv / B, v = uv - u * B;
+      double s = 0.0;
+      for (int r = 0; r < B; ++r) {
+        const double p = sDd[u * B + r] * T[r * P + v];
+        s = s + p;
+      }
+      cnt += fabs(s) > thr ? 1 : 0;
+    }
+    cnt = wave_sum_i32(cnt);
+    if (lane == 0) stat[im.blk_off + tl.first + bb] = cnt;
+    wave_lds_sync();
+  }
+}
+
+// y[off_i + z] = C_i[zigzag(z)] for z < k_i.
+template <int B>
+__global__ __launch_bounds__(kGroupThreads) void k_gen_sense(const ImgDev* __restrict__ imgs,
+                                                            const Tile* __restrict__ tiles, int ntiles,
+                                                            const uint8_t* __restrict__ px,
+                                                            const int32_t* __restrict__ k_all,
+                                                            const int64_t* __restrict__ off_all,
+                                                            float* __restrict__ y) {
+  constexpr int P = B + 1;
+  __shared__ GenShared<B> sh;
+  if ((int)blockIdx.x >= ntiles) return;
+  gen_load_tables<B>(sh);
+  __syncthreads();
+  const Tile tl = tiles[blockIdx.x];
+  const ImgDev im = imgs[tl.img];
+  const int w = wave_in_group(), lane = threadIdx.x & 63;
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, (B - 1) * im.pitch + B * tl.count);
+  float* a = sh.a[w];
+  float* b = sh.b[w];
+  float* ym = y + im.meas_off;
+  for (int bb = w; bb < tl.count; bb += kWavesPerGroup) {
+    gen_load_pixels<B>(rp, im.pitch, bb, a);
+    wave_lds_sync();
+    gen_fwd<B>(sh.D, a, b);
+    // rank-ordered copy in b (as a flat array of B*B)
+    for (int idx = lane; idx < B * B; idx += 64) {
+      const int u = idx / B, v = idx - u * B;
+      b[sh.rank[idx]] = a[u * P + v];
+    }
+    wave_lds_sync();
+    int kk;
+    int64_t rel;
+    gen_block_range(im, k_all, off_all, im.blk_off + tl.first + bb, B * B, kk, rel);
+    for (int z = lane; z < kk; z += 64) ym[rel + z] = b[z];
+    wave_lds_sync();
+  }
+}
+
+// out = D^T C D per block, C zero beyond the block's k_i zigzag entries.
+template <int B>
+__global__ __launch_bounds__(kGroupThreads) void k_gen_reconstruct(const ImgDev* __restrict__ imgs,
+                                                                  const Tile* __restrict__ tiles, int ntiles,
+                                                                  const float* __restrict__ y,
+                                                                  const int32_t* __restrict__ k_all,
+                                                                  const int64_t* __restrict__ off_all,
+                                                                  float* __restrict__ out) {
+  constexpr int P = B + 1;
+  __shared__ GenShared<B> sh;
+  if ((int)blockIdx.x >= ntiles) return;
+  gen_load_tables<B>(sh);
+  __syncthreads();
+  const Tile tl = tiles[blockIdx.x];
+  const ImgDev im = imgs[tl.img];
+  const int w = wave_in_group(), lane = threadIdx.x & 63;
+  float* a = sh.a[w];
+  float* b = sh.b[w];
+  const float* ym = y + im.meas_off;
+  for (int bb = w; bb < tl.count; bb += kWavesPerGroup) {
+    int kk;
+    int64_t rel;
+    gen_block_range(im, k_all, off_all, im.blk_off + tl.first + bb, B * B, kk, rel);
+    for (int z = lane; z < B * B; z += 64) b[z] = z < kk ? ym[rel + z] : 0.f;
+    wave_lds_sync();
+    for (int idx = lane; idx < B * B; idx += 64) {
+      const int u = idx / B, v = idx - u * B;
+      a[u * P + v] = b[sh.rank[idx]];
+    }
+    wave_lds_sync();
+    gen_inv<B>(sh.D, a, b);
+    float* o = out + tl.out_base + B * bb;
+    for (int idx = lane; idx < B * B; idx += 64) {
+      const int x = idx / B, xp = idx - x * B;
+      o[(int64_t)x * im.Wc + xp] = a[x * P + xp];
+    }
+    wave_lds_sync();
+  }
+}
+
+// The transform half of an IDA iteration (as k_ida_step16): z^t = y - A x^t
+// + alpha z^{t-1} on the measured coefficients, v = x + A* z^t, and the
+// block's sum of (z^t)^2 in float64 (fixed butterfly order) in part[blk].
+template <int B>
+__global__ __launch_bounds__(kGroupThreads) void k_gen_ida_step(const ImgDev* __restrict__ imgs,
+                                                               const Tile* __restrict__ tiles, int ntiles,
+                                                               const float* __restrict__ y,
+                                                               const int32_t* __restrict__ k_all,
+                                                               const int64_t* __restrict__ off_all,
+                                                               const float* x, float* __restrict__ z,
+                                                               float* v, double* __restrict__ part, float alpha,
+                                                               int first) {
+  constexpr int P = B + 1;
+  __shared__ GenShared<B> sh;
+  if ((int)blockIdx.x >= ntiles) return;
+  gen_load_tables<B>(sh);
+  __syncthreads();
+  const Tile tl = tiles[blockIdx.x];
+  const ImgDev im = imgs[tl.img];
+  const int w = wave_in_group(), lane = threadIdx.x & 63;
+  float* a = sh.a[w];
+  float* b = sh.b[w];
+  const float* ym = y + im.meas_off;
+  float* zm = z + im.meas_off;
+  for (int bb = w; bb < tl.count; bb += kWavesPerGroup) {
+    const int64_t base = tl.out_base + B * bb;
+    for (int idx = lane; idx < B * B; idx += 64) {
+      const int r = idx / B, c = idx - r * B;
+      a[r * P + c] = first ? 0.f : x[base + (int64_t)r * im.Wc + c];
+    }
+    wave_lds_sync();
+    gen_fwd<B>(sh.D, a, b);
+    for (int idx = lane; idx < B * B; idx += 64) {
+      const int u = idx / B, vv = idx - u * B;
+      b[sh.rank[idx]] = a[u * P + vv];
+    }
+    wave_lds_sync();
+    int kk;
+    int64_t rel;
+    const int64_t blk = im.blk_off + tl.first + bb;
+    gen_block_range(im, k_all, off_all, blk, B * B, kk, rel);
+    double acc = 0.0;
+    for (int zi = lane; zi < kk; zi += 64) {
+      const float zo = first ? 0.f : zm[rel + zi];
+      const float zn = (ym[rel + zi] - b[zi]) + alpha * zo;
+      zm[rel + zi] = zn;
+      b[zi] = b[zi] + zn;
+      acc += (double)zn * (double)zn;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) part[blk] = acc;
+    wave_lds_sync();
+    for (int idx = lane; idx < B * B; idx += 64) {
+      const int u = idx / B, vv = idx - u * B;
+      a[u * P + vv] = b[sh.rank[idx]];
+    }
+    wave_lds_sync();
+    gen_inv<B>(sh.D, a, b);
+    for (int idx = lane; idx < B * B; idx += 64) {
+      const int r = idx / B, c = idx - r * B;
+      v[base + (int64_t)r * im.Wc + c] = a[r * P + c];
+    }
+    wave_lds_sync();
+  }
+}
+
+}  // namespace abcs

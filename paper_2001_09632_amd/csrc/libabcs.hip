@@ -8,4 +8,5 @@
 #include "ida_kernels.hpp"
 #include "bm3d_kernels.hpp"
 #include "cnn_kernels.hpp"
+#include "generic_kernels.hpp"
 #include "api.cpp.inc"

@@ -68,7 +68,8 @@ class Run:
     def image(self, i):
         d = self.plan.images[i]
         b0 = d["block_offset"]
-        nb = (d["cropped_height"] // 16) * (d["cropped_width"] // 16)
+        B = d["block"]
+        nb = (d["cropped_height"] // B) * (d["cropped_width"] // B)
         m0, nm = d["meas_offset"], d["n_meas"]
         o0 = d["out_offset"]
         hc, wc = d["cropped_height"], d["cropped_width"]

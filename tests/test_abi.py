@@ -53,7 +53,8 @@ def _err(desc):
 
 def test_descriptor_validation(native):
     base = dict(height=256, width=256, block=16, subrate=0.25, method="bbv")
-    assert _err({**base, "block": 8}) == native.ABCS_EUNSUPPORTED
+    assert _err({**base, "block": 12}) == native.ABCS_EUNSUPPORTED
+    assert _err({**base, "block": 64}) == native.ABCS_EUNSUPPORTED
     assert _err({**base, "subrate": 0.0}) == native.ABCS_EDOMAIN
     assert _err({**base, "subrate": 1.5}) == native.ABCS_EDOMAIN
     assert _err({**base, "subrate": 0.6}) == native.ABCS_EDOMAIN      # BBV needs L >= 2
