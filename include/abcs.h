@@ -168,7 +168,8 @@ int abcs_reconstruct(const abcs_plan* plan, const float* d_y, const int32_t* d_k
  *                bytes, 256-byte aligned; overwritten.
  * Errors: EINVAL, EDOMAIN (D_F < 1 or NaN), EUNSUPPORTED (denoiser not
  * built, or the CNN on a plan with an image whose W' is not a multiple of 16
- * or H' of 8, possible with B = 8), ENOSPACE (workspace too small), EHIP. */
+ * or H' of 8 (possible with B = 8) or that has 2^24 pixels or more),
+ * ENOSPACE (workspace too small), EHIP. */
 size_t ida_workspace_bytes(const abcs_plan* plan, int denoiser);
 /* Resumable form: runs iterations t = t_begin .. t_end-1 of the same loop.
  * t_begin = 0 starts from x^0 = 0 and z^{-1} = 0; t_begin > 0 continues from

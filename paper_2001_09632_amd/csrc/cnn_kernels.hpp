@@ -38,13 +38,8 @@ struct CnnTile {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ unsigned short f2bf(float f) {
-  // round to nearest even
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);  // NaN stays NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
+// float32 -> bfloat16, round to nearest even (v_cvt_pk_bf16_f32; NaN stays NaN).
+__device__ __forceinline__ unsigned short f2bf(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
 
 // float32 blob -> bfloat16 copies: mid-layer weights in blob order
@@ -70,45 +65,82 @@ __global__ __launch_bounds__(256) void k_cnn_prep(const float* __restrict__ blob
   if (i < 9 * 64) w8r[i] = bf2f(f2bf(blob[kW8 + i]));
 }
 
-// Layer 1 (2 -> 64): thread per pixel, output bfloat16 NHWC.
-__global__ __launch_bounds__(256) void k_cnn_first(const ImgDev* __restrict__ imgs, int n_imgs,
-                                                  const int32_t* __restrict__ pix_img, int64_t pixels,
-                                                  const float* __restrict__ v, const float* __restrict__ sigma,
-                                                  const float* __restrict__ w1r, const float* __restrict__ blob,
-                                                  unsigned short* __restrict__ act) {
+// Layer 1 (2 -> 64) on float32 MFMA (v_mfma_f32_16x16x4_f32); a workgroup
+// loops over 8 x 16-pixel tiles.  K = 18 = 9 taps x 2 input channels (padded to 20), in
+// the order k = 2 tap + c; input channel 0 is v / 255, channel 1 the constant
+// map min(sigma, 255) / 255 (both zero outside the image).  Wave w computes
+// rows 2w, 2w + 1: for 16 output channels x 16 pixels a product has the
+// weights as A (lane (g, n): channel n, k = 4 chunk + g) and the inputs as B.
+// The outputs go through LDS so that each pixel's 64 channels (128 bytes)
+// leave in whole-line stores.
+__global__ __launch_bounds__(256) void k_cnn_first(const ImgDev* __restrict__ imgs, const CnnTile* __restrict__ tiles,
+                                                  int ntiles, const float* __restrict__ v,
+                                                  const float* __restrict__ sigma, const float* __restrict__ w1r,
+                                                  const float* __restrict__ blob, unsigned short* __restrict__ act) {
   using namespace cnn;
-  __shared__ float sw[64 * 18];
-  __shared__ float sb[64];
-  for (int t = threadIdx.x; t < 64 * 18; t += 256) sw[t] = w1r[t];
-  if (threadIdx.x < 64) sb[threadIdx.x] = blob[kB1 + threadIdx.x];
-  __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= pixels) return;
-  const ImgDev im = imgs[pix_img[p >> kPixChunkShift]];
-  const int64_t lp = p - im.out_off;
-  const int y = (int)(lp / im.Wc), x = (int)(lp - (int64_t)y * im.Wc);
-  const float s = fminf(sigma[pix_img[p >> kPixChunkShift]], 255.f) * (1.f / 255.f);
-  float in0[9], in1[9];
+  constexpr int TH = kTileH + 2, TW = kTileW + 2;
+  constexpr int kOutStride = kCh + 8;  // bf16 per staged output pixel
+  __shared__ float vin[TH * TW];
+  __shared__ __attribute__((aligned(16))) unsigned short obuf[kTileH * kTileW * kOutStride];
+  __shared__ float sb[kCh];
+  if (threadIdx.x < kCh) sb[threadIdx.x] = blob[kB1 + threadIdx.x];
+  const int wave = wave_in_group();
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+  // A: weight of output channel 16 cg + n at k = 4 c + g
+  float wa[4][5];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-    const bool ok = yy >= 0 && yy < im.Hc && xx >= 0 && xx < im.Wc;
-    in0[t] = ok ? v[im.out_off + (int64_t)yy * im.Wc + xx] * (1.f / 255.f) : 0.f;
-    in1[t] = ok ? s : 0.f;
-  }
-  u16x8* dst = (u16x8*)(act + p * kCh);
+  for (int cg = 0; cg < 4; ++cg)
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    u16x8 o;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int co = q * 8 + k;
-      float a = sb[co];
-#pragma unroll
-      for (int t = 0; t < 9; ++t) a = fmaf(sw[co * 18 + t * 2], in0[t], fmaf(sw[co * 18 + t * 2 + 1], in1[t], a));
-      o[k] = f2bf(fmaxf(a, 0.f));
+    for (int c = 0; c < 5; ++c) {
+      const int k = 4 * c + g;
+      wa[cg][c] = k < 18 ? w1r[(16 * cg + n) * 18 + k] : 0.f;
     }
-    dst[q] = o;
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const CnnTile tl = tiles[ti];
+    const ImgDev im = imgs[tl.img];
+    const float sg = fminf(sigma[tl.img], 255.f) * (1.f / 255.f);
+    __syncthreads();  // previous tile's outputs stored
+    for (int t = threadIdx.x; t < TH * TW; t += 256) {
+      const int ty = t / TW, tx = t - ty * TW;
+      const int y = tl.y0 + ty - 1, x = tl.x0 + tx - 1;
+      vin[t] = ((unsigned)y < (unsigned)im.Hc && (unsigned)x < (unsigned)im.Wc)
+                   ? v[im.out_off + (int64_t)y * im.Wc + x] * (1.f / 255.f)
+                   : 0.f;
+    }
+    __syncthreads();
+  #pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int row = 2 * wave + r;
+      float bv[5];
+  #pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const int k = 4 * c + g, tap = k >> 1, ch = k & 1;
+        const int dy = tap / 3, dx = tap % 3;
+        const bool inside = k < 18 && (unsigned)(tl.y0 + row + dy - 1) < (unsigned)im.Hc &&
+                            (unsigned)(tl.x0 + n + dx - 1) < (unsigned)im.Wc;
+        bv[c] = !inside ? 0.f : (ch == 0 ? vin[(row + dy) * TW + n + dx] : sg);
+      }
+  #pragma unroll
+      for (int cg = 0; cg < 4; ++cg) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  #pragma unroll
+        for (int c = 0; c < 5; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[cg][c], bv[c], acc, 0, 0, 0);
+        // acc[q]: channel 16 cg + 4 g + q of pixel (row, n)
+        const int c0 = 16 * cg + 4 * g;
+        uint2 pk;
+        pk.x = (uint32_t)f2bf(fmaxf(acc[0] + sb[c0], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1] + sb[c0 + 1], 0.f)) << 16);
+        pk.y = (uint32_t)f2bf(fmaxf(acc[2] + sb[c0 + 2], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3] + sb[c0 + 3], 0.f)) << 16);
+        *(uint2*)(obuf + (row * kTileW + n) * kOutStride + c0) = pk;
+      }
+    }
+    __syncthreads();
+    // 128 pixels x 8 parts of 16 bytes
+    for (int t = threadIdx.x; t < kTileH * kTileW * 8; t += 256) {
+      const int px = t >> 3, part = t & 7;
+      const int y = tl.y0 + px / kTileW, x = tl.x0 + px % kTileW;
+      *(u16x8*)(act + (im.out_off + (int64_t)y * im.Wc + x) * kCh + part * 8) =
+          *(const u16x8*)(obuf + px * kOutStride + part * 8);
+    }
   }
 }
 
@@ -122,7 +154,7 @@ __global__ __launch_bounds__(256) void k_cnn_first(const ImgDev* __restrict__ im
 // MODE 1 (input gradient): weights are the transposed, tap-flipped copy,
 //         out = bf16(sum) where mask > 0 (the ReLU of the layer below), else 0.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_cnn_mid(const ImgDev* __restrict__ imgs, const CnnTile* __restrict__ tiles,
+__global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ imgs, const CnnTile* __restrict__ tiles,
                                                 int ntiles, const unsigned short* __restrict__ in,
                                                 const unsigned short* __restrict__ w, const float* __restrict__ bias,
                                                 const unsigned short* __restrict__ mask,
@@ -144,27 +176,41 @@ __global__ __launch_bounds__(256) void k_cnn_mid(const ImgDev* __restrict__ imgs
 #pragma unroll
       for (int kc = 0; kc < 2; ++kc)
         wa[cg][tap][kc] = *(const bf16x8*)(w + ((cbase + 16 * cg + n) * 9 + tap) * kCh + 32 * kc + 8 * g);
-  float bs[2][4];
-#pragma unroll
-  for (int cg = 0; cg < 2; ++cg)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) bs[cg][q] = MODE == 0 ? bias[cbase + 16 * cg + 4 * g + q] : 0.f;
+  __shared__ float sbias[kCh];
+  if (threadIdx.x < kCh) sbias[threadIdx.x] = MODE == 0 ? bias[threadIdx.x] : 0.f;
 
+  // The input tile (with its one-pixel halo, zero outside the image) of the
+  // next tile is loaded into registers while the current one is computed.
+  constexpr int NST = (TH * TW * 8 + 255) / 256;
+  u16x8 pre[NST];
+  auto fetch = [&](int tj) {
+    const CnnTile tn = tiles[tj];
+    const ImgDev imn = imgs[tn.img];
+    // the image's activations; offsets outside it read as zero
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(in + imn.out_off * kCh, imn.Hc * imn.Wc * kCh * 2);
+#pragma unroll
+    for (int sidx = 0; sidx < NST; ++sidx) {
+      const int t = threadIdx.x + 256 * sidx;
+      const int px = t >> 3, part = t & 7;
+      const int ty = px / TW, tx = px - ty * TW;
+      const int y = tn.y0 + ty - 1, x = tn.x0 + tx - 1;
+      const bool ok = t < TH * TW * 8 && (unsigned)y < (unsigned)imn.Hc && (unsigned)x < (unsigned)imn.Wc;
+      const uint32_t off = ok ? (uint32_t)(((y * imn.Wc + x) * kCh + part * 8) * 2) : 0xffffffffu;
+      pre[sidx] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, off, 0, 0));
+    }
+  };
+  if ((int)blockIdx.x < ntiles) fetch(blockIdx.x);
   for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
     const CnnTile tl = tiles[ti];
     const ImgDev im = imgs[tl.img];
     __syncthreads();  // previous tile fully consumed
-    // stage the input tile with halo: 16 bytes (8 channels) per thread and pass
-    for (int t = threadIdx.x; t < TH * TW * 8; t += 256) {
-      const int px = t >> 3, part = t & 7;
-      const int ty = px / TW, tx = px - ty * TW;
-      const int y = tl.y0 + ty - 1, x = tl.x0 + tx - 1;
-      u16x8 val = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (y >= 0 && y < im.Hc && x >= 0 && x < im.Wc)
-        val = *(const u16x8*)(in + (im.out_off + (int64_t)y * im.Wc + x) * kCh + part * 8);
-      *(u16x8*)(tile + px * kPxStride + part * 8) = val;
+#pragma unroll
+    for (int sidx = 0; sidx < NST; ++sidx) {
+      const int t = threadIdx.x + 256 * sidx;
+      if (t < TH * TW * 8) *(u16x8*)(tile + (t >> 3) * kPxStride + (t & 7) * 8) = pre[sidx];
     }
     __syncthreads();
+    if (ti + (int)gridDim.x < ntiles) fetch(ti + gridDim.x);
     // Two rows at a time: 4 independent accumulators per wave.
 #pragma unroll 1
     for (int r2 = 0; r2 < 4; r2 += 2) {
@@ -199,7 +245,7 @@ __global__ __launch_bounds__(256) void k_cnn_mid(const ImgDev* __restrict__ imgs
           unsigned short o[4];
           if (MODE == 0) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) o[q] = f2bf(fmaxf(acc[r][cg][q] + bs[cg][q], 0.f));
+            for (int q = 0; q < 4; ++q) o[q] = f2bf(fmaxf(acc[r][cg][q] + sbias[c0 + q], 0.f));
           } else {
             const uint2 mk = *(const uint2*)(mask + pix * kCh + c0);
             const unsigned short m4[4] = {(unsigned short)(mk.x & 0xffff), (unsigned short)(mk.x >> 16),
@@ -217,36 +263,66 @@ __global__ __launch_bounds__(256) void k_cnn_mid(const ImgDev* __restrict__ imgs
   }
 }
 
-// Layer 8 (64 -> 1) and the residual: out = v - 255 (b8 + sum w8 a7).
-// Thread per pixel.
-__global__ __launch_bounds__(256) void k_cnn_last(const ImgDev* __restrict__ imgs, const int32_t* __restrict__ pix_img,
-                                                 int64_t pixels, const float* __restrict__ v,
+// Layer 8 (64 -> 1) and the residual, out = v - 255 (b8 + sum w8 a7), on
+// bfloat16 MFMA.  A workgroup loops over 8 x 16-pixel tiles, each staged with
+// its halo in LDS as in k_cnn_mid.  The A operand holds the 32 weights of
+// (tap, K chunk) in row 0 only (lanes n = 0, read from LDS), so row 0 of the
+// product is the layer's output for 16 pixels; wave w computes rows 2w, 2w+1.
+__global__ __launch_bounds__(256) void k_cnn_last(const ImgDev* __restrict__ imgs, const CnnTile* __restrict__ tiles,
+                                                 int ntiles, const float* __restrict__ v,
                                                  const unsigned short* __restrict__ act,
                                                  const float* __restrict__ w8r, const float* __restrict__ blob,
                                                  float* __restrict__ out) {
   using namespace cnn;
-  __shared__ float sw[9 * 64];
-  for (int t = threadIdx.x; t < 9 * 64; t += 256) sw[t] = w8r[t];
-  __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= pixels) return;
-  const ImgDev im = imgs[pix_img[p >> kPixChunkShift]];
-  const int64_t lp = p - im.out_off;
-  const int y = (int)(lp / im.Wc), x = (int)(lp - (int64_t)y * im.Wc);
-  float f = blob[kB8];
+  constexpr int TH = kTileH + 2, TW = kTileW + 2;
+  __shared__ __attribute__((aligned(16))) unsigned short tile[TH * TW * kPxStride];
+  __shared__ __attribute__((aligned(16))) unsigned short w8s[9 * kCh];
+  for (int t = threadIdx.x; t < 9 * kCh; t += 256) w8s[t] = f2bf(w8r[t]);
+  const int wave = wave_in_group();
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+  const float b8 = blob[kB8];
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const CnnTile tl = tiles[ti];
+    const ImgDev im = imgs[tl.img];
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(act + im.out_off * kCh, im.Hc * im.Wc * kCh * 2);
+    __syncthreads();  // previous tile consumed (and w8s written)
+    for (int t = threadIdx.x; t < TH * TW * 8; t += 256) {
+      const int px = t >> 3, part = t & 7;
+      const int ty = px / TW, tx = px - ty * TW;
+      const int y = tl.y0 + ty - 1, x = tl.x0 + tx - 1;
+      const bool ok = (unsigned)y < (unsigned)im.Hc && (unsigned)x < (unsigned)im.Wc;
+      const uint32_t off = ok ? (uint32_t)(((y * im.Wc + x) * kCh + part * 8) * 2) : 0xffffffffu;
+      *(u16x8*)(tile + px * kPxStride + part * 8) =
+          __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, off, 0, 0));
+    }
+    __syncthreads();
+    f32x4 acc[2];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-    if (yy < 0 || yy >= im.Hc || xx < 0 || xx >= im.Wc) continue;
-    const u16x8* a = (const u16x8*)(act + (im.out_off + (int64_t)yy * im.Wc + xx) * kCh);
+    for (int r = 0; r < 2; ++r) acc[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const u16x8 h = a[q];
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) f = fmaf(sw[t * 64 + q * 8 + k], bf2f(h[k]), f);
+      for (int kc = 0; kc < 2; ++kc) {
+        const u16x8 wz = {0, 0, 0, 0, 0, 0, 0, 0};
+        const u16x8 wv = *(const u16x8*)(w8s + tap * kCh + 32 * kc + 8 * g);
+        const bf16x8 wa = __builtin_bit_cast(bf16x8, n == 0 ? wv : wz);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const bf16x8 b =
+              *(const bf16x8*)(tile + ((2 * wave + r + dy) * TW + (n + dx)) * kPxStride + 8 * g + 32 * kc);
+          acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, b, acc[r], 0, 0, 0);
+        }
+      }
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int64_t p = im.out_off + (int64_t)(tl.y0 + 2 * wave + r) * im.Wc + tl.x0 + n;
+        out[p] = v[p] - 255.f * (b8 + acc[r][0]);
+      }
     }
   }
-  out[p] = v[p] - 255.f * f;
 }
 
 // Fallback selection: sig_fb[i] = sigma[i] when image i's network output holds
