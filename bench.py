@@ -214,7 +214,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-images", type=int, default=16)
+    ap.add_argument("--cpu-images", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ida", action="store_true")
     ap.add_argument("--cnn-weights", default=os.path.join(ROOT, "paper_2001_09632_amd", "weights", "ida_cnn.npy"))
