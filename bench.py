@@ -187,6 +187,118 @@ def ida_section(dev, weights_path):
     return rec
 
 
+STREAM_SIZES = [(256, 256), (512, 512), (768, 1024), (2048, 2048)]   # (H, W); 1024x768 read as W x H
+STREAM_BUDGET_BYTES = 1 << 30   # device bytes of y + decoded images admitted per batch
+
+
+def stream_requests(n, seed=5):
+    """n requests of the mixed stream: size uniform over STREAM_SIZES, B over
+    {8, 16, 32}, C_R ~ U(0.05, 0.5), budget rule over {ZZ, BBV, DD}."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return [dict(size=int(rng.integers(0, 4)), block=int(rng.choice([8, 16, 32])),
+                 subrate=float(rng.uniform(0.05, 0.5)), method=str(rng.choice(["zz", "bbv", "dd"])))
+            for _ in range(n)]
+
+
+def stream_section(dev, n_requests=1000, load=0.5):
+    """The mixed request stream: every request is encoded (budget + sense) and
+    decoded (masked inverse DCT) on the GPU.  Requests are batched in arrival
+    order while their y and decoded images fit STREAM_BUDGET_BYTES; one plan
+    per batch (its creation is part of the timed work).  Image content comes
+    from a pool of one synthetic image per size held in device memory.  First
+    all requests arrive at once (saturated Mpixel/s), then as a Poisson stream
+    (seed 7) at `load` times the saturated pixel rate; latency = completion -
+    arrival."""
+    import numpy as np
+    import torch
+    import paper_2001_09632_amd as g
+    import synth
+    pool = [synth.synth_image(3000 + i, h, w) for i, (h, w) in enumerate(STREAM_SIZES)]
+    offs, o = [], 0
+    for im in pool:
+        offs.append(o)
+        o += im.size
+    px = torch.from_numpy(np.concatenate([im.reshape(-1) for im in pool])).to(dev)
+    reqs = stream_requests(n_requests)
+
+    def entry(r):
+        h, w = STREAM_SIZES[r["size"]]
+        return dict(height=h, width=w, row_pitch=w, block=r["block"], subrate=r["subrate"], method=r["method"],
+                    pixel_offset=offs[r["size"]])
+
+    def cost(r):
+        h, w = STREAM_SIZES[r["size"]]
+        return 4 * h * w + 4 * int(r["subrate"] * h * w) + 64
+
+    def batches(order):
+        out, cur, used = [], [], 0
+        for i in order:
+            c = cost(reqs[i])
+            if cur and used + c > STREAM_BUDGET_BYTES:
+                out.append(cur)
+                cur, used = [], 0
+            cur.append(i)
+            used += c
+        if cur:
+            out.append(cur)
+        return out
+
+    max_blocks = max(sum((STREAM_SIZES[reqs[i]["size"]][0] // reqs[i]["block"]) *
+                         (STREAM_SIZES[reqs[i]["size"]][1] // reqs[i]["block"]) for i in b)
+                     for b in batches(range(n_requests)))
+    kb = torch.empty(max_blocks, dtype=torch.int32, device=dev)
+    ob = torch.empty(max_blocks, dtype=torch.int64, device=dev)
+    sb = torch.empty(max_blocks, dtype=torch.int32, device=dev)
+    yb = torch.empty(STREAM_BUDGET_BYTES // 4, dtype=torch.float32, device=dev)
+    xb = torch.empty(STREAM_BUDGET_BYTES // 4, dtype=torch.float32, device=dev)
+
+    def run_batch(idx):
+        plan = g.Plan([entry(reqs[i]) for i in idx])
+        g.budget(plan, px, kb, ob, sb)
+        g.sense(plan, px, kb, ob, yb)
+        g.reconstruct(plan, yb, kb, ob, xb)
+        torch.cuda.synchronize()
+        return plan.pixels
+
+    run_batch(list(range(min(8, n_requests))))          # warm up
+    t0 = time.perf_counter()
+    total_px = 0
+    for b in batches(range(n_requests)):
+        total_px += run_batch(b)
+    sat_s = time.perf_counter() - t0
+    sat_rate = total_px / sat_s
+
+    # Poisson arrivals at `load` of the saturated pixel rate
+    rng = np.random.default_rng(7)
+    mean_px = total_px / n_requests
+    gaps = rng.exponential(mean_px / (load * sat_rate), size=n_requests)
+    arrive = np.cumsum(gaps)
+    done = np.zeros(n_requests)
+    nxt = 0
+    t0 = time.perf_counter()
+    while nxt < n_requests:
+        now = time.perf_counter() - t0
+        if arrive[nxt] > now:
+            time.sleep(arrive[nxt] - now)
+            now = time.perf_counter() - t0
+        ready = [i for i in range(nxt, n_requests) if arrive[i] <= now]
+        batch = batches(ready)[0]
+        run_batch(batch)
+        done[batch] = time.perf_counter() - t0
+        nxt = batch[-1] + 1
+    span = done.max()
+    lat = (done - arrive) * 1e3
+    return {"workload": f"{n_requests} requests: 256x256 / 512x512 / 1024x768 / 2048x2048 uniform, B 8/16/32, "
+                        "C_R ~ U(0.05,0.5), ZZ/BBV/DD; budget+sense+inverse DCT, plan per batch",
+            "pixels": int(total_px), "batch_budget_bytes": STREAM_BUDGET_BYTES,
+            "saturated": {"mpixel_per_s": round(sat_rate / 1e6, 1), "seconds": round(sat_s, 4),
+                          "batches": len(batches(range(n_requests)))},
+            "stream": {"offered_load": load, "mpixel_per_s": round(total_px / span / 1e6, 1),
+                       "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                      "p99": round(float(np.percentile(lat, 99)), 3)}}}
+
+
 def cpu_baseline(images, n_images, deadline_s=30.0):
     """The FP64 oracle (budget + sensing + decoding) on the first n_images of
     the batch at every (estimator, subrate) pair; single-threaded numpy."""
@@ -215,6 +327,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-images", type=int, default=48)
+    ap.add_argument("--no-stream", action="store_true", help="skip the mixed request-stream section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ida", action="store_true")
     ap.add_argument("--cnn-weights", default=os.path.join(ROOT, "paper_2001_09632_amd", "weights", "ida_cnn.npy"))
@@ -298,6 +411,11 @@ def main():
         log("ida")
         ida = ida_section(dev, args.cnn_weights)
 
+    stream = None
+    if not args.no_stream:
+        log("stream")
+        stream = stream_section(dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -324,6 +442,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ida": ida,
+        "stream": stream,
     }
     print(json.dumps(rec), flush=True)
 

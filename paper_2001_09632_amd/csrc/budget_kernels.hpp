@@ -165,8 +165,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_dd_stats(const ImgDev* __rest
 //      largest (P w_i mod S), ties to the lower index (radix select on the
 //      remainder, then a rank among equal remainders).
 //   4. DD adds the m^1 phase-1 coefficients; offsets = exclusive prefix sum.
-// Thread t owns the contiguous index range [t*per, t*per + per) so that index
-// order is thread order.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T wave_sum_t(T v) {
@@ -206,6 +204,15 @@ __device__ T group_exclusive_scan(T v, T* sh) {
   return base + inc - v;
 }
 
+// floor(pw / S) for 0 <= pw < 2^53 and 0 < S < 2^53: the float64 quotient is
+// within one of the exact one, which the integer checks then settle.
+__device__ __forceinline__ int64_t floor_div_exact(int64_t pw, int64_t S) {
+  int64_t q = (int64_t)((double)pw / (double)S);
+  if (q * S > pw) q -= 1;
+  if ((q + 1) * S <= pw) q += 1;
+  return q;
+}
+
 __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __restrict__ imgs,
                                                             int32_t* __restrict__ stat_all,
                                                             int32_t* __restrict__ k_all,
@@ -217,13 +224,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
   const int nB = im.nB;
   int32_t* w = stat_all + im.blk_off;
   int32_t* k = k_all + im.blk_off;
-  int64_t* off = off_all + im.blk_off;
+  int64_t* off = off_all + im.blk_off;  // also holds the remainders until the offsets are written
   const int tid = threadIdx.x;
-  const int per = (nB + kGroupThreads - 1) / kGroupThreads;
-  const int i0 = min(nB, tid * per), i1 = min(nB, i0 + per);
 
   if (im.mode == kModeZZ) {
-    for (int i = i0; i < i1; ++i) {
+    for (int i = tid; i < nB; i += kGroupThreads) {
       k[i] = im.kz;
       w[i] = 0;
       off[i] = im.meas_off + (int64_t)i * im.kz;
@@ -231,45 +236,52 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
     return;
   }
 
+  // Passes without an order over the blocks use interleaved indices
+  // (coalesced); the two passes that need index order (ties, offsets) give
+  // thread t the contiguous range [t per, t per + per).
   const int64_t cap = im.cap;
   int64_t P = im.pool;
-  for (int i = i0; i < i1; ++i) k[i] = -1;  // undecided
+  for (int i = tid; i < nB; i += kGroupThreads) k[i] = -1;  // undecided
 
   int64_t S = 0;
   bool uniform = false;
   for (;;) {
     int64_t sw = 0, na = 0;
-    for (int i = i0; i < i1; ++i)
+    for (int i = tid; i < nB; i += kGroupThreads)
       if (k[i] < 0) { sw += w[i]; na += 1; }
     S = group_sum(sw, sh64);
     const int64_t A = group_sum(na, sh64);
     if (A == 0) break;
     uniform = (S == 0);
     if (uniform) S = A;
-    int64_t used = 0, nover = 0;
-    for (int i = i0; i < i1; ++i) {
+    // floor(P w_i / S) >= cap  <=>  P w_i >= cap S: every such block is fixed
+    // at its cap with the same P and S, then the split is redone.
+    const int64_t capS = cap * S;
+    int64_t used = 0;
+    for (int i = tid; i < nB; i += kGroupThreads) {
       if (k[i] < 0) {
         const int64_t wi = uniform ? 1 : (int64_t)w[i];
-        if ((P * wi) / S >= cap) nover += 1;
+        if (P * wi >= capS) { k[i] = (int32_t)cap; used += cap; }
       }
     }
-    nover = group_sum(nover, sh64);
-    if (nover == 0) break;
-    for (int i = i0; i < i1; ++i) {
-      if (k[i] < 0) {
-        const int64_t wi = uniform ? 1 : (int64_t)w[i];
-        if ((P * wi) / S >= cap) { k[i] = (int32_t)cap; used += cap; }
-      }
-    }
-    P -= group_sum(used, sh64);
+    used = group_sum(used, sh64);
+    if (used == 0) break;
+    P -= used;
   }
 
-  // Floors of the final split and the leftover R.
+  // Floors and remainders of the final split, once: k[i] = floor(P w_i / S),
+  // off[i] = remainder (-1 for blocks fixed at the cap).
   int64_t sq = 0;
-  for (int i = i0; i < i1; ++i) {
+  for (int i = tid; i < nB; i += kGroupThreads) {
     if (k[i] < 0) {
       const int64_t wi = uniform ? 1 : (int64_t)w[i];
-      sq += (P * wi) / S;
+      const int64_t pw = P * wi;
+      const int64_t q = floor_div_exact(pw, S);
+      k[i] = (int32_t)q;
+      off[i] = pw - q * S;
+      sq += q;
+    } else {
+      off[i] = -1;
     }
   }
   const int64_t R = P - group_sum(sq, sh64);
@@ -282,13 +294,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
       hist[tid] = 0;  // kGroupThreads == 256 bins
       __syncthreads();
       const uint64_t hi_mask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
-      for (int i = i0; i < i1; ++i) {
-        if (k[i] < 0) {
-          const int64_t wi = uniform ? 1 : (int64_t)w[i];
-          const int64_t pw = P * wi;
-          const uint64_t rem = (uint64_t)(pw - (pw / S) * S);
-          if ((rem & hi_mask) == ((uint64_t)tau & hi_mask)) atomicAdd(&hist[(rem >> shift) & 255u], 1);
-        }
+      for (int i = tid; i < nB; i += kGroupThreads) {
+        const int64_t rem = off[i];
+        if (rem >= 0 && ((uint64_t)rem & hi_mask) == ((uint64_t)tau & hi_mask))
+          atomicAdd(&hist[((uint64_t)rem >> shift) & 255u], 1);
       }
       __syncthreads();
       // Bin counts summed from the top digit down: the selected digit d is
@@ -311,34 +320,24 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
   }
 
   // Final values: floor + 1 for remainders above tau and for the first `need`
-  // (by index) remainders equal to tau.
+  // (by index) remainders equal to tau; then the offsets, both in index order.
+  const int per = (nB + kGroupThreads - 1) / kGroupThreads;
+  const int i0 = min(nB, tid * per), i1 = min(nB, i0 + per);
   int64_t neq = 0;
-  if (R > 0) {
-    for (int i = i0; i < i1; ++i) {
-      if (k[i] < 0) {
-        const int64_t wi = uniform ? 1 : (int64_t)w[i];
-        const int64_t pw = P * wi;
-        if (pw - (pw / S) * S == tau) neq += 1;
-      }
-    }
-  }
+  if (R > 0)
+    for (int i = i0; i < i1; ++i) neq += (off[i] == tau) ? 1 : 0;
   int64_t rank = group_exclusive_scan(neq, sh64);
   const int32_t add = (im.mode == kModeDD) ? im.m1 : 0;
   int64_t ksum = 0;
   for (int i = i0; i < i1; ++i) {
     int64_t ki = k[i];
-    if (ki < 0) {
-      const int64_t wi = uniform ? 1 : (int64_t)w[i];
-      const int64_t pw = P * wi;
-      const int64_t q = pw / S, rem = pw - q * S;
-      ki = q;
-      if (R > 0) {
-        if (rem > tau) {
-          ki += 1;
-        } else if (rem == tau) {
-          if (rank < need) ki += 1;
-          rank += 1;
-        }
+    const int64_t rem = off[i];
+    if (R > 0 && rem >= 0) {
+      if (rem > tau) {
+        ki += 1;
+      } else if (rem == tau) {
+        if (rank < need) ki += 1;
+        rank += 1;
       }
     }
     ki += add;
