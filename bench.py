@@ -406,6 +406,31 @@ def main():
                     algorithmic_bytes=algorithmic_bytes(plan, dom))
     per_kernel_ms = dict(budget=round(ms_budget, 4), sense=round(ms_sense, 4), reconstruct=round(ms_recon, 4))
 
+    # The 16-bit operand modes of the same two transforms (budget unchanged):
+    # time per call, and the largest deviation of y and of the decoded images
+    # from the float32 path.  Context only; the headline is float32.
+    prec = {}
+    y32, out32 = y.clone(), out.clone()
+    y_m = torch.empty_like(y)
+    out_m = torch.empty_like(out)
+    for mode in ("bf16x3", "fp16x3", "bf16", "fp16"):
+        g.sense(plan, px, k, off, y_m, stream, precision=mode)
+        g.reconstruct(plan, y_m, k, off, out_m, stream, precision=mode)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        for _ in range(5):
+            g.sense(plan, px, k, off, y_m, stream, precision=mode)
+        e[1].record(stream)
+        for _ in range(5):
+            g.reconstruct(plan, y_m, k, off, out_m, stream, precision=mode)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        prec[mode] = {"sense_ms": round(e[0].elapsed_time(e[1]) / 5, 4),
+                      "reconstruct_ms": round(e[1].elapsed_time(e[2]) / 5, 4),
+                      "max_abs_dy_vs_fp32": round(float((y_m - y32).abs().max()), 5),
+                      "max_abs_dpx_vs_fp32": round(float((out_m - out32).abs().max()), 5)}
+
     ida = None
     if not args.no_ida:
         log("ida")
@@ -439,6 +464,7 @@ def main():
                    "images": len(SEEDS), "height": H, "width": W, "block": B, "encodings_per_step": plan.n,
                    "pixels_per_step": pixels_per_step},
         "per_kernel_ms": per_kernel_ms,
+        "precision_modes": prec,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ida": ida,

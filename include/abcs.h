@@ -69,6 +69,21 @@ typedef enum abcs_denoiser {
   ABCS_DENOISE_CNN = 2       /* learned 8-layer 3x3 CNN (parameters passed)  */
 } abcs_denoiser;
 
+/* Arithmetic of the B = 16 block transforms in abcs_sense and
+ * abcs_reconstruct (B = 8 and 32 always use float32 operands with float64
+ * sums).  The 16-bit modes run on the matrix cores with float32 sums; the
+ * "x3" modes split each operand that is not exact in 16 bits into a high and a
+ * low part and keep every product but low x low (about float32 accuracy); the
+ * single-pass modes round the operands once.  Budgets (abcs_budget) never
+ * depend on the mode.                                                        */
+typedef enum abcs_precision {
+  ABCS_FP32 = 0,
+  ABCS_BF16X3 = 1,
+  ABCS_FP16X3 = 2,
+  ABCS_BF16 = 3,
+  ABCS_FP16 = 4
+} abcs_precision;
+
 /* One image of a batch.  The caller fills the first block of fields;
  * abcs_plan_create fills the layout fields of its own copy, which
  * abcs_plan_image returns. */
@@ -138,17 +153,19 @@ int abcs_budget(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes,
 
 /* Phase 2 sensing (Alg 1 step 4; Alg 2 step 5): y[offsets[i] + z] =
  * C_i[zigzag[z]] for z < k[i], where C_i = D X_i D^T is block i's orthonormal
- * 2D DCT-II of the raw [0, 255] pixels (float32 arithmetic).
+ * 2D DCT-II of the raw [0, 255] pixels, computed in `precision`
+ * (abcs_precision; EINVAL for other values).
  * d_y: out, float[meas]. */
 int abcs_sense(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes,
-               const int32_t* d_k, const int64_t* d_offsets, float* d_y, void* stream);
+               const int32_t* d_k, const int64_t* d_offsets, float* d_y, int precision, void* stream);
 
 /* Real-time decoder (Fig 1, I_o): zero-fill each block's unmeasured
- * coefficients and apply the inverse 2D DCT X = D^T C D (float32).
+ * coefficients and apply the inverse 2D DCT X = D^T C D, computed in
+ * `precision` (abcs_precision).
  * Needs only y, k and offsets (the side information), never pixels.
  * d_out: out, float[pixels], each image H' x W' with row pitch W'. */
 int abcs_reconstruct(const abcs_plan* plan, const float* d_y, const int32_t* d_k,
-                     const int64_t* d_offsets, float* d_out, void* stream);
+                     const int64_t* d_offsets, float* d_out, int precision, void* stream);
 
 /* IDA post-processing (Section VI; eqs 13, 15, 25, 28; Fig 6).
  * Starting from x^0 = 0 and z^{-1} = 0, iteration t = 0 .. iters-1 computes

@@ -58,8 +58,8 @@ def lib():
     L.abcs_plan_totals.argtypes = [vp, P64, P64, P64]
     L.abcs_plan_image.argtypes = [vp, i32, ctypes.POINTER(ImageDesc)]
     L.abcs_budget.argtypes = [vp, vp, i64, vp, vp, vp, vp]
-    L.abcs_sense.argtypes = [vp, vp, i64, vp, vp, vp, vp]
-    L.abcs_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.abcs_sense.argtypes = [vp, vp, i64, vp, vp, vp, i32, vp]
+    L.abcs_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, vp]
     L.abcs_dct_basis.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
     L.abcs_last_error.restype = ctypes.c_char_p
     L.ida_workspace_bytes.argtypes = [vp, i32]

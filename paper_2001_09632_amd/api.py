@@ -78,16 +78,24 @@ def budget(plan, px, k, offsets, stat, stream=None):
                             _ptr(offsets), _ptr(stat), _stream(stream)))
 
 
-def sense(plan, px, k, offsets, y, stream=None):
-    """abcs_sense: y float32[meas] device tensor (written)."""
+PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16": 3, "fp16": 4}
+
+
+def _prec(precision):
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
+def sense(plan, px, k, offsets, y, stream=None, precision="fp32"):
+    """abcs_sense: y float32[meas] device tensor (written); precision one of
+    PRECISIONS (the B = 16 transform's arithmetic)."""
     check(lib().abcs_sense(plan.handle, _ptr(px), px.numel() * px.element_size(), _ptr(k),
-                           _ptr(offsets), _ptr(y), _stream(stream)))
+                           _ptr(offsets), _ptr(y), _prec(precision), _stream(stream)))
 
 
-def reconstruct(plan, y, k, offsets, out, stream=None):
+def reconstruct(plan, y, k, offsets, out, stream=None, precision="fp32"):
     """abcs_reconstruct: out float32[pixels] device tensor (written)."""
     check(lib().abcs_reconstruct(plan.handle, _ptr(y), _ptr(k), _ptr(offsets), _ptr(out),
-                                 _stream(stream)))
+                                 _prec(precision), _stream(stream)))
 
 
 IDENTITY, BM3D, CNN = 0, 1, 2

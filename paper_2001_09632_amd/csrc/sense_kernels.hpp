@@ -26,6 +26,7 @@ struct WaveLds {
 // LDS at its zigzag rank and leaves with unit-stride stores of the block's k_i
 // coefficients (slot z of store q is lane + 64 q); slots at or beyond k_i get
 // an out-of-range offset and are dropped.
+template <int P>
 __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restrict__ imgs,
                                                           const Tile* __restrict__ tiles, int ntiles,
                                                           const uint8_t* __restrict__ px,
@@ -40,6 +41,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane16_init(L);
+  Lane16P<P> H;
+  if (P != kPrecFP32) lane16p_init(H, L);
   TileIO io;
   tile_io_init(io, im, tl, px, y, k_all, off_all, L);
   float* buf = lds[wave_in_group()].c;
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
     float a[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) a[c] = (float)((pw >> (8 * c)) & 0xffu);
-    const f32x4 C = dct16_fwd(a, L);
+    const f32x4 C = P == kPrecFP32 ? dct16_fwd(a, L) : dct16_fwd_p<P>(a, H);
 #pragma unroll
     for (int r = 0; r < 4; ++r) buf[L.zr[r]] = C[r];
     wave_lds_sync();
@@ -88,6 +91,7 @@ __device__ __forceinline__ float row_ror8(float v) {
 // Cache policy bits of a buffer store: non-temporal.
 constexpr int kStoreNT = 2;
 
+template <int P>
 __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* __restrict__ imgs,
                                                                 const Tile* __restrict__ tiles, int ntiles,
                                                                 const float* __restrict__ y,
@@ -102,6 +106,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane16_init(L);
+  Lane16P<P> H;
+  if (P != kPrecFP32) lane16p_init(H, L);
   TileIO io;
   tile_io_init(io, im, tl, nullptr, y, k_all, off_all, L);
   const int lane = threadIdx.x & 63;
@@ -141,8 +147,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
       e1[c] = buf1[L.zr[c]];
     }
     wave_lds_sync();
-    const f32x4 A = idct16_inv(e0, L);
-    const f32x4 Bv = idct16_inv(e1, L);
+    const f32x4 A = P == kPrecFP32 ? idct16_inv(e0, L) : idct16_inv_p<P>(e0, H);
+    const f32x4 Bv = P == kPrecFP32 ? idct16_inv(e1, L) : idct16_inv_p<P>(e1, H);
     f32x4 S1, S2;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

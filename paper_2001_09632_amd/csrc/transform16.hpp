@@ -72,6 +72,114 @@ __device__ __forceinline__ f32x4 idct16_inv(const float e[4], const Lane16& L) {
   return out;
 }
 
+// ---------------------------------------------------------------------------
+// 16-bit operand modes of the same transforms (v_mfma_f32_16x16x16_f16 /
+// _bf16, float32 sums).  Lane l = 16g + n supplies A[n][4g .. 4g+3] and
+// B[4g .. 4g+3][n] and receives D[4g+r][n]: the K index is 4g + c, as in the
+// float32 chain above, so the operand and output layouts are unchanged.
+// Pixels (integers 0..255) are exact in both formats.  The compensated modes
+// split every other float32 operand v into hi = round16(v) and
+// lo = round16(v - hi) and drop only the lo x lo product: the forward
+// transform takes 2 + 3 products, the inverse 3 + 3.  The single-pass modes
+// use hi only.
+// ---------------------------------------------------------------------------
+enum Precision : int { kPrecFP32 = 0, kPrecBF16x3 = 1, kPrecFP16x3 = 2, kPrecBF16 = 3, kPrecFP16 = 4 };
+
+template <int P>
+struct Prec16 {
+  static constexpr bool kBF = (P == kPrecBF16x3 || P == kPrecBF16);
+  static constexpr bool kSplit = (P == kPrecBF16x3 || P == kPrecFP16x3);
+};
+
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+template <bool BF>
+__device__ __forceinline__ unsigned short to16(float x) {
+  if (BF) return __builtin_bit_cast(unsigned short, (__bf16)x);
+  return __builtin_bit_cast(unsigned short, (_Float16)x);
+}
+template <bool BF>
+__device__ __forceinline__ float from16(unsigned short h) {
+  if (BF) return __uint_as_float((uint32_t)h << 16);
+  return (float)__builtin_bit_cast(_Float16, h);
+}
+template <bool BF>
+__device__ __forceinline__ f32x4 mfma16(u16x4 a, u16x4 b, f32x4 c) {
+  if (BF) return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, a), __builtin_bit_cast(s16x4, b), c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(f16x4, a), __builtin_bit_cast(f16x4, b), c, 0, 0, 0);
+}
+
+// hi / lo parts of four float32 values
+template <bool BF>
+__device__ __forceinline__ void split16(const float v[4], u16x4& hi, u16x4& lo) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    hi[c] = to16<BF>(v[c]);
+    lo[c] = to16<BF>(v[c] - from16<BF>(hi[c]));
+  }
+}
+
+// Per-lane basis operands: fwd = D[n][4g .. 4g+3], inv = D[4g .. 4g+3][n].
+template <int P>
+struct Lane16P {
+  u16x4 fwd_hi, fwd_lo, inv_hi, inv_lo;
+};
+
+template <int P>
+__device__ __forceinline__ void lane16p_init(Lane16P<P>& H, const Lane16& L) {
+  constexpr bool BF = Prec16<P>::kBF;
+  split16<BF>(L.dR, H.fwd_hi, H.fwd_lo);
+  split16<BF>(L.dT, H.inv_hi, H.inv_lo);
+}
+
+// Forward: in a[c] = X[n][4g+c] (pixel values), out C[4g+r][n].
+template <int P>
+__device__ __forceinline__ f32x4 dct16_fwd_p(const float a[4], const Lane16P<P>& H) {
+  constexpr bool BF = Prec16<P>::kBF;
+  u16x4 x;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) x[c] = to16<BF>(a[c]);
+  f32x4 t = {0.f, 0.f, 0.f, 0.f};
+  t = mfma16<BF>(x, H.fwd_hi, t);                                // T = X D^T
+  if (Prec16<P>::kSplit) t = mfma16<BF>(x, H.fwd_lo, t);
+  float tv[4] = {t[0], t[1], t[2], t[3]};
+  u16x4 th, tlo;
+  split16<BF>(tv, th, tlo);
+  f32x4 out = {0.f, 0.f, 0.f, 0.f};
+  out = mfma16<BF>(H.fwd_hi, th, out);                           // C = D T
+  if (Prec16<P>::kSplit) {
+    out = mfma16<BF>(H.fwd_hi, tlo, out);
+    out = mfma16<BF>(H.fwd_lo, th, out);
+  }
+  return out;
+}
+
+// Inverse: in e[c] = C[4g+c][n], out X[n][4g+r].
+template <int P>
+__device__ __forceinline__ f32x4 idct16_inv_p(const float e[4], const Lane16P<P>& H) {
+  constexpr bool BF = Prec16<P>::kBF;
+  u16x4 ch, clo;
+  split16<BF>(e, ch, clo);
+  f32x4 q = {0.f, 0.f, 0.f, 0.f};
+  q = mfma16<BF>(ch, H.inv_hi, q);                                // Q = C^T D
+  if (Prec16<P>::kSplit) {
+    q = mfma16<BF>(clo, H.inv_hi, q);
+    q = mfma16<BF>(ch, H.inv_lo, q);
+  }
+  float qv[4] = {q[0], q[1], q[2], q[3]};
+  u16x4 qh, qlo;
+  split16<BF>(qv, qh, qlo);
+  f32x4 out = {0.f, 0.f, 0.f, 0.f};
+  out = mfma16<BF>(H.inv_hi, qh, out);                            // X^T = D^T Q
+  if (Prec16<P>::kSplit) {
+    out = mfma16<BF>(H.inv_hi, qlo, out);
+    out = mfma16<BF>(H.inv_lo, qh, out);
+  }
+  return out;
+}
+
 // Per-tile addressing of the 16x16-block kernels.  Every block of a tile
 // reads and writes through resources set up once per tile; a block's own
 // addresses differ from the tile's by compile-time multiples of 16 pixels, and
