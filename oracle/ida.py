@@ -15,10 +15,27 @@ started from x^0 = 0 (the ISTA convention stated with eqs 9-10) and z^{-1} = 0,
 so z^0 = y, v^0 = A* y = I_o, the real-time reconstruction.  The loop output is
 the last denoised iterate x^T; nothing is clipped inside the loop.
 
+D-AMP and DAMP-D (`amp`) keep the Onsager coefficient of eqs 14 / 24 (and
+its damped form, eq 27) instead of eq 28's constant:
+
+    alpha^t = div D_{sigma^{t-1}}(v^{t-1}) / m          (D-AMP)
+    alpha^t = div D_{sigma^{t-1}}(v^{t-1}) / (m D_F)    (DAMP-D),   alpha^0 = 0
+
+Reading: eq 14 prints both a 1/delta factor and a division by m.  The AMP
+correction it generalises (Section III) is (1/delta) times the component mean
+of the denoiser's derivative over the N signal components, i.e.
+(1/delta)(div / N) = div / m with delta = m / N; that is the coefficient used
+here.  The divergence is the Monte-Carlo estimate of D-AMP's authors (ref
+[13]): div D(v) ~ b . (D(v + eps b) - D(v)) / eps with eps = max|v| / 1000
+(1e-3 when v is 0) and a probe vector b of standard normal values, passed in
+and reused at every iteration.
+
 Parity: pinned with the identity denoiser against the closed-form scalar
-recurrence of each measured coefficient (tests/test_oracle_ida.py).  With a
-real denoiser the oracle is the same loop, so it is as pinned as that
-denoiser.
+recurrence of each measured coefficient (tests/test_oracle_ida.py), for IDA
+and, with alpha = ||b||^2 / m (the exact Monte-Carlo divergence of the
+identity), for D-AMP and DAMP-D; a linear denoiser D(v) = lambda v pins the
+divergence path (lambda ||b||^2).  With a real denoiser the oracle is the same
+loop, so it is as pinned as that denoiser.
 """
 
 import math
@@ -59,3 +76,41 @@ def ida(y, k, block, height, width, iters, damping, denoiser=identity_denoiser,
         z_prev = z
         sigmas.append(sigma)
     return x, sigmas
+
+
+def amp(y, k, block, height, width, iters, damping, probe, denoiser=identity_denoiser,
+        algorithm="damp"):
+    """Run `iters` iterations of D-AMP (algorithm "damp", eqs 13-15, 24) or
+    DAMP-D ("damp-d", eq 27) for one image.
+
+    probe   the Monte-Carlo probe b, shape (H', W')
+    returns (x^T, list of sigma^t, list of alpha^t)
+    """
+    if algorithm not in ("damp", "damp-d"):
+        raise ValueError(algorithm)
+    Hc, Wc, nbx, nby, _ = abcs.geometry(height, width, block)
+    y = np.asarray(y, dtype=np.float64)
+    b = np.asarray(probe, dtype=np.float64).reshape(Hc, Wc)
+    m = y.size
+    scale = 1.0 if algorithm == "damp" else 1.0 / float(damping)
+    x = np.zeros((Hc, Wc), dtype=np.float64)
+    z_prev = np.zeros(m, dtype=np.float64)
+    alpha = 0.0
+    sigmas, alphas = [], []
+    for t in range(int(iters)):
+        r = y - abcs.sense_op(x, block, k)
+        z = r + alpha * z_prev
+        sigma = math.sqrt(float(np.sum(z * z)) / m) if m else 0.0
+        v = x + abcs.sense_adjoint(z, block, k, nby, nbx)
+        x_new = np.asarray(denoiser(v, sigma), dtype=np.float64)
+        sigmas.append(sigma)
+        alphas.append(alpha)
+        if t + 1 < iters:
+            vmax = float(np.max(np.abs(v)))
+            eps = vmax / 1000.0 if vmax > 0 else 1e-3
+            xp = np.asarray(denoiser(v + eps * b, sigma), dtype=np.float64)
+            div = float(np.sum(b * (xp - x_new))) / eps
+            alpha = scale * div / m if m else 0.0
+        x = x_new
+        z_prev = z
+    return x, sigmas, alphas

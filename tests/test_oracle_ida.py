@@ -58,3 +58,54 @@ def test_iterates_stay_in_measured_subspace(case):
         for z in range(int(ki), 256):
             r, c = zz[z]
             assert abs(C[i, r, c]) < 1e-8
+
+
+def _recurrence_ratios(alpha, steps):
+    """c^t / y for t = 1..steps with z^0 = y, c^1 = y and, from t = 1 on,
+    z^t = (y - c^t) + alpha z^{t-1}, c^{t+1} = c^t + z^t (y = 1)."""
+    c, z_prev, out = 0.0, 0.0, []
+    for t in range(steps):
+        a = 0.0 if t == 0 else alpha
+        z = (1.0 - c) + a * z_prev
+        c += z
+        z_prev = z
+        out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("algorithm,damping", [("damp", 2.0), ("damp-d", 2.0), ("damp-d", 8.0)])
+def test_amp_identity_follows_recurrence(case, algorithm, damping):
+    """Identity denoiser: the Monte-Carlo divergence is exactly ||b||^2, so
+    alpha^t = ||b||^2 / m (/ D_F) from t = 1 on and every measured
+    coefficient follows the scalar recurrence."""
+    img, k, y = case
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(img.shape)
+    steps = 4
+    m = y.size
+    a = float(np.sum(b * b)) / m / (1.0 if algorithm == "damp" else damping)
+    for t in range(1, steps + 1):
+        x, _, alphas = ida.amp(y, k, 16, 64, 48, t, damping, b, algorithm=algorithm)
+        assert alphas[0] == 0.0
+        assert np.allclose(alphas[1:], a, rtol=1e-9)
+        c = abcs.sense_op(x, 16, k)
+        ratio = _recurrence_ratios(a, t)[-1]
+        assert np.allclose(c, ratio * y, rtol=1e-9, atol=1e-6 * max(1.0, abs(ratio)) * np.max(np.abs(y)))
+
+
+def test_amp_linear_denoiser_divergence(case):
+    """D(v) = lambda v: div = lambda ||b||^2, so alpha^1 = lambda ||b||^2 / m."""
+    img, k, y = case
+    b = np.random.default_rng(4).standard_normal(img.shape)
+    lam = 0.75
+    _, _, alphas = ida.amp(y, k, 16, 64, 48, 2, 2.0, b, denoiser=lambda v, s: lam * v)
+    assert math.isclose(alphas[1], lam * float(np.sum(b * b)) / y.size, rel_tol=1e-9)
+
+
+def test_damp_d_infinite_damping_is_ida_without_memory(case):
+    """DAMP-D with D_F = inf has alpha = 0: the same iterates as IDA at D_F = inf."""
+    img, k, y = case
+    b = np.random.default_rng(5).standard_normal(img.shape)
+    xa, sa, _ = ida.amp(y, k, 16, 64, 48, 5, math.inf, b, denoiser=lambda v, s: 0.9 * v, algorithm="damp-d")
+    xi, si = ida.ida(y, k, 16, 64, 48, 5, math.inf, denoiser=lambda v, s: 0.9 * v)
+    assert np.allclose(xa, xi, rtol=0, atol=1e-9) and np.allclose(sa, si, rtol=1e-12)
