@@ -202,6 +202,31 @@ int ida_refine(const abcs_plan* plan, const float* d_y, const int32_t* d_k, cons
                int iters, double damping, int denoiser, const void* d_params, float* d_x,
                float* d_sigma_trace, void* d_ws, size_t ws_bytes, void* stream);
 
+/* D-AMP and DAMP-D (eqs 13-15 with the Onsager coefficient of eq 24, or its
+ * damped form eq 27), the algorithms IDA is derived from.  Same loop as
+ * ida_refine, but the weight of z^{t-1} is, per image,
+ *   alpha^t = div D_{sigma^{t-1}}(v^{t-1}) / m          (ABCS_ALGO_DAMP)
+ *   alpha^t = div D_{sigma^{t-1}}(v^{t-1}) / (m D_F)    (ABCS_ALGO_DAMP_D)
+ * with alpha^0 = 0.  (Eq 14 prints both 1/delta and /m; the AMP correction it
+ * generalises, (1/delta) times the mean derivative over the N pixels, is
+ * div / m.)  The divergence is estimated as in ref [13]:
+ * b . (D(v + eps b) - D(v)) / eps with eps = max|v| / 1000 per image (1e-3
+ * when v is 0): one more denoiser call per iteration.
+ * d_probe:       in, float[pixels] (plan layout): the probe b, normally
+ *                standard normal values; the caller draws it; it is reused at
+ *                every iteration.
+ * d_alpha_trace: out, nullable, float[iters * n]: alpha^t of image i at
+ *                t * n + i.
+ * damping:       D_F >= 1 (DAMP-D only; +inf gives alpha = 0).
+ * d_ws:          amp_workspace_bytes(plan, denoiser) bytes, 256-byte aligned.
+ * Other arguments and errors as ida_refine. */
+typedef enum abcs_algorithm { ABCS_ALGO_DAMP = 1, ABCS_ALGO_DAMP_D = 2 } abcs_algorithm;
+size_t amp_workspace_bytes(const abcs_plan* plan, int denoiser);
+int amp_refine(const abcs_plan* plan, const float* d_y, const int32_t* d_k, const int64_t* d_offsets, int iters,
+               double damping, int algorithm, int denoiser, const void* d_params, const float* d_probe,
+               float* d_x, float* d_sigma_trace, float* d_alpha_trace, void* d_ws, size_t ws_bytes,
+               void* stream);
+
 /* The IDA loop as a replayable HIP graph: ida_graph_create records the
  * launches of ida_refine(plan, d_y, d_k, d_offsets, iters, damping, denoiser,
  * d_params, d_x, d_sigma_trace, d_ws, ws_bytes) into one instantiated graph

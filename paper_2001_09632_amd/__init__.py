@@ -9,4 +9,5 @@ raise if the library is missing.
 from .api import (ZZ, BBV, DD, Plan, AbcsError, budget, sense, reconstruct,  # noqa: F401
                   dct_basis, METHODS, ida_refine, ida_iterate, ida_workspace_bytes, DENOISERS,
                   denoise, denoise_workspace_bytes, cnn_param_count, cnn_train_step,
-                  cnn_train_workspace_bytes, IdaGraph, PRECISIONS)
+                  cnn_train_workspace_bytes, IdaGraph, PRECISIONS,
+                  amp_refine, amp_workspace_bytes, ALGORITHMS)

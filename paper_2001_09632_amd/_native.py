@@ -13,7 +13,7 @@ EXPORTS = [
     "abcs_budget", "abcs_sense", "abcs_reconstruct", "abcs_dct_basis", "abcs_last_error",
     "ida_workspace_bytes", "ida_refine", "ida_iterate", "abcs_denoise_workspace_bytes", "abcs_denoise",
     "abcs_cnn_param_count", "abcs_cnn_train_workspace_bytes", "abcs_cnn_train_step",
-    "ida_graph_create", "ida_graph_launch", "ida_graph_destroy",
+    "ida_graph_create", "ida_graph_launch", "ida_graph_destroy", "amp_workspace_bytes", "amp_refine",
 ]
 
 
@@ -77,11 +77,15 @@ def lib():
     L.ida_graph_create.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp, sz,
                                    ctypes.POINTER(vp)]
     L.ida_graph_launch.argtypes = [vp, vp]
+    L.amp_workspace_bytes.argtypes = [vp, i32]
+    L.amp_workspace_bytes.restype = sz
+    L.amp_refine.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     L.ida_graph_destroy.argtypes = [vp]
     L.ida_graph_destroy.restype = None
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("abcs_plan_destroy", "abcs_last_error", "ida_workspace_bytes", "ida_graph_destroy",
+                        "amp_workspace_bytes",
                         "abcs_denoise_workspace_bytes", "abcs_cnn_param_count",
                         "abcs_cnn_train_workspace_bytes"):
             f.restype = ctypes.c_int

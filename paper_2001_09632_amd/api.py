@@ -118,6 +118,26 @@ def ida_refine(plan, y, k, offsets, x, iters, damping=2.0, denoiser="identity", 
                            _stream(stream)))
 
 
+ALGORITHMS = {"damp": 1, "damp-d": 2}
+
+
+def amp_workspace_bytes(plan, denoiser):
+    d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
+    return int(lib().amp_workspace_bytes(plan.handle, d))
+
+
+def amp_refine(plan, y, k, offsets, x, iters, probe, damping=2.0, algorithm="damp", denoiser="identity",
+               params=None, sigma_trace=None, alpha_trace=None, workspace=None, stream=None):
+    """amp_refine: D-AMP ("damp") or DAMP-D ("damp-d"); probe float32[pixels]
+    (the Monte-Carlo divergence probe, drawn by the caller)."""
+    d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
+    a = ALGORITHMS[algorithm] if isinstance(algorithm, str) else int(algorithm)
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().amp_refine(plan.handle, _ptr(y), _ptr(k), _ptr(offsets), int(iters), float(damping), a, d,
+                           _ptr(params), _ptr(probe), _ptr(x), _ptr(sigma_trace), _ptr(alpha_trace),
+                           _ptr(workspace), ws_bytes, _stream(stream)))
+
+
 class IdaGraph:
     """ida_graph_create / ida_graph_launch / ida_graph_destroy: the whole
     ida_refine loop recorded once as a HIP graph and replayed per launch().

@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_ida_step(const ImgDev* __
                                                                const int64_t* __restrict__ off_all,
                                                                const float* x, float* __restrict__ z,
                                                                float* v, double* __restrict__ part, float alpha,
-                                                               int first) {
+                                                               const float* __restrict__ alpha_img, int first) {
   constexpr int P = B + 1;
   __shared__ GenShared<B> sh;
   if ((int)blockIdx.x >= ntiles) return;
@@ -303,6 +303,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_ida_step(const ImgDev* __
   __syncthreads();
   const Tile tl = tiles[blockIdx.x];
   const ImgDev im = imgs[tl.img];
+  if (alpha_img) alpha = alpha_img[tl.img];
   const int w = wave_in_group(), lane = threadIdx.x & 63;
   float* a = sh.a[w];
   float* b = sh.b[w];

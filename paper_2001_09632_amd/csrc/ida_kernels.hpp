@@ -21,6 +21,8 @@ namespace abcs {
 // z (in: z^{t-1}, out: z^t) is laid out like y; part[blk] receives the block's
 // sum of (z^t)^2 in float64, summed in a fixed order.  When `first` is set,
 // x^0 = 0 and z^{-1} = 0 are used without reading x or z.  v may alias x.
+// The weight of z^{t-1} is alpha_img[image] when alpha_img is not null
+// (D-AMP's per-image Onsager coefficient), else alpha.
 __global__ __launch_bounds__(kGroupThreads) void k_ida_step16(const ImgDev* __restrict__ imgs,
                                                              const Tile* __restrict__ tiles, int ntiles,
                                                              const float* __restrict__ y,
@@ -28,11 +30,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_ida_step16(const ImgDev* __re
                                                              const int64_t* __restrict__ off_all,
                                                              const float* x, float* __restrict__ z,
                                                              float* v, double* __restrict__ part,
-                                                             float alpha, int first) {
+                                                             float alpha, const float* __restrict__ alpha_img,
+                                                             int first) {
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
   const Tile tl = tiles[wave];
   const ImgDev im = imgs[tl.img];
+  if (alpha_img) alpha = alpha_img[tl.img];
   Lane16 L;
   lane16_init(L);
   TileIO io;
@@ -118,6 +122,74 @@ __global__ __launch_bounds__(kGroupThreads) void k_ida_sigma(const ImgDev* __res
 __global__ __launch_bounds__(256) void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// D-AMP / DAMP-D (eqs 14, 24, 27): the Onsager coefficient from a Monte-Carlo
+// divergence, div D(v) ~ b . (D(v + eps b) - D(v)) / eps (ref [13]).
+// ---------------------------------------------------------------------------
+
+// eps[i] = max |v| over image i / 1000 (1e-3 when v is 0); one workgroup per
+// image (a maximum: independent of the order).
+__global__ __launch_bounds__(kGroupThreads) void k_amp_eps(const ImgDev* __restrict__ imgs,
+                                                          const float* __restrict__ v, float* __restrict__ eps) {
+  __shared__ float sh[kGroupThreads];
+  const ImgDev im = imgs[blockIdx.x];
+  const int64_t n = (int64_t)im.Hc * im.Wc;
+  float m = 0.f;
+  for (int64_t i = threadIdx.x; i < n; i += kGroupThreads) m = fmaxf(m, fabsf(v[im.out_off + i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kGroupThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) eps[blockIdx.x] = sh[0] > 0.f ? sh[0] / 1000.f : 1e-3f;
+}
+
+// vp = v + eps[image] b
+__global__ __launch_bounds__(256) void k_amp_perturb(const int32_t* __restrict__ pix_img, int64_t pixels,
+                                                    const float* __restrict__ v, const float* __restrict__ b,
+                                                    const float* __restrict__ eps, float* __restrict__ vp) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= pixels) return;
+  vp[p] = v[p] + eps[pix_img[p >> kPixChunkShift]] * b[p];
+}
+
+// alpha[i] = scale * (sum over image i of b (xp - x)) / (eps[i] m_i), the sum in
+// float64 in a fixed order (strided per thread, then a tree); also
+// trace[t * n_imgs + i] when trace is not null.  One workgroup per image.
+__global__ __launch_bounds__(kGroupThreads) void k_amp_alpha(const ImgDev* __restrict__ imgs,
+                                                            const float* __restrict__ b,
+                                                            const float* __restrict__ xp,
+                                                            const float* __restrict__ x,
+                                                            const float* __restrict__ eps, float scale,
+                                                            float* __restrict__ alpha, float* __restrict__ trace,
+                                                            int n_imgs, int t) {
+  __shared__ double sh[kGroupThreads];
+  const ImgDev im = imgs[blockIdx.x];
+  const int64_t n = (int64_t)im.Hc * im.Wc;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kGroupThreads) {
+    const int64_t p = im.out_off + i;
+    s += (double)b[p] * ((double)xp[p] - (double)x[p]);
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kGroupThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float a = im.n_meas > 0 ? (float)((double)scale * (sh[0] / (double)eps[blockIdx.x]) / (double)im.n_meas) : 0.f;
+    alpha[blockIdx.x] = a;
+    if (trace) trace[(int64_t)t * n_imgs + blockIdx.x] = a;
+  }
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 }  // namespace abcs
