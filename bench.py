@@ -73,9 +73,9 @@ COPY_KIB = 1048576.0
 TRAFFIC = {
     "reconstruct": dict(
         sources=("common.hpp", "transform16.hpp", "sense_kernels.hpp"),
-        sha256="5805031d135f45270c4b445348391141606c9ff86da5e8d802a242e46c735310",
-        fetch_kib=98434.5625, write_kib=655360.0,
-        copy_fetch_kib=524301.25, copy_write_kib=1048576.0),
+        sha256="9e0117b2eab08a1ac31a4ebd1a9ade82684d7fe8a6b60b4b36cd9a62997ca8e6",
+        fetch_kib=98088.66, write_kib=655520.47,
+        copy_fetch_kib=524301.24, copy_write_kib=1048576.0),
 }
 
 
@@ -184,6 +184,31 @@ def ida_section(dev, weights_path):
                       "psnr_by_iters": trail}
     rec["matched_psnr"] = matched
     rec["learned_over_plain_images_per_s"] = round(tp / tl, 2)
+
+    # The loop variants of Section VI with the learned denoiser at the chosen
+    # iteration count: IDA against D-AMP (eq 24) and DAMP-D (eq 27, D_F = 2),
+    # and IDA's PSNR as a function of D_F (the sweep of Fig 8).
+    probe = torch.from_numpy(np.random.default_rng(11).standard_normal(plan.pixels).astype(np.float32)).to(dev)
+    wsa = torch.empty(g.amp_workspace_bytes(plan, "cnn"), dtype=torch.uint8, device=dev)
+    xa = torch.empty(plan.pixels, dtype=torch.float32, device=dev)
+    variants = {}
+    for name, alg in (("d-amp", "damp"), ("damp-d", "damp-d")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.amp_refine(plan, y, k, off, xa, it, probe, damping=2.0, algorithm=alg, denoiser="cnn", params=prm,
+                     workspace=wsa)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pa, sa = scores(xa)
+        variants[name] = {"iters": it, "psnr": round(pa, 3), "ssim": round(sa, 4), "ms_per_batch": round(dt * 1e3, 2)}
+    variants["ida"] = {"iters": it, "psnr": round(pl, 3), "ssim": round(sl, 4), "ms_per_batch": round(tl * 1e3, 2)}
+    rec["loop_variants"] = variants
+    wsi = torch.empty(g.ida_workspace_bytes(plan, "cnn"), dtype=torch.uint8, device=dev)
+    sweep = {}
+    for df in (1.0, 1.25, 1.5, 2.0, 3.0, 4.0):
+        g.ida_refine(plan, y, k, off, xa, it, df, "cnn", params=prm, workspace=wsi)
+        sweep[str(df)] = round(scores(xa)[0], 3)
+    rec["ida_psnr_by_damping"] = sweep
     return rec
 
 
