@@ -129,15 +129,37 @@ __global__ __launch_bounds__(256) void k_copy_f32(const float* __restrict__ src,
 // divergence, div D(v) ~ b . (D(v + eps b) - D(v)) / eps (ref [13]).
 // ---------------------------------------------------------------------------
 
-// eps[i] = max |v| over image i / 1000 (1e-3 when v is 0); one workgroup per
-// image (a maximum: independent of the order).
+// Per 64-pixel chunk (every image holds whole chunks): the chunk's max |v|
+// and the chunk's sum of b (xp - x) in float64, in index order.  One thread
+// per chunk.
+__global__ __launch_bounds__(256) void k_amp_chunks(int64_t chunks, const float* __restrict__ v,
+                                                   const float* __restrict__ b, const float* __restrict__ xp,
+                                                   const float* __restrict__ x, float* __restrict__ cmax,
+                                                   double* __restrict__ csum) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= chunks) return;
+  const int64_t p0 = c << kPixChunkShift;
+  if (cmax) {
+    float m = 0.f;
+    for (int i = 0; i < (1 << kPixChunkShift); ++i) m = fmaxf(m, fabsf(v[p0 + i]));
+    cmax[c] = m;
+  } else {
+    double s = 0.0;
+    for (int i = 0; i < (1 << kPixChunkShift); ++i)
+      s += (double)b[p0 + i] * ((double)xp[p0 + i] - (double)x[p0 + i]);
+    csum[c] = s;
+  }
+}
+
+// eps[i] = max |v| over image i / 1000 (1e-3 when v is 0), from the chunk
+// maxima; one workgroup per image.
 __global__ __launch_bounds__(kGroupThreads) void k_amp_eps(const ImgDev* __restrict__ imgs,
-                                                          const float* __restrict__ v, float* __restrict__ eps) {
+                                                          const float* __restrict__ cmax, float* __restrict__ eps) {
   __shared__ float sh[kGroupThreads];
   const ImgDev im = imgs[blockIdx.x];
-  const int64_t n = (int64_t)im.Hc * im.Wc;
+  const int64_t c0 = im.out_off >> kPixChunkShift, nc = ((int64_t)im.Hc * im.Wc) >> kPixChunkShift;
   float m = 0.f;
-  for (int64_t i = threadIdx.x; i < n; i += kGroupThreads) m = fmaxf(m, fabsf(v[im.out_off + i]));
+  for (int64_t i = threadIdx.x; i < nc; i += kGroupThreads) m = fmaxf(m, cmax[c0 + i]);
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int w = kGroupThreads / 2; w > 0; w >>= 1) {
@@ -156,24 +178,20 @@ __global__ __launch_bounds__(256) void k_amp_perturb(const int32_t* __restrict__
   vp[p] = v[p] + eps[pix_img[p >> kPixChunkShift]] * b[p];
 }
 
-// alpha[i] = scale * (sum over image i of b (xp - x)) / (eps[i] m_i), the sum in
-// float64 in a fixed order (strided per thread, then a tree); also
-// trace[t * n_imgs + i] when trace is not null.  One workgroup per image.
+// alpha[i] = scale * (sum over image i of b (xp - x)) / (eps[i] m_i): the
+// chunk sums of the image added in a fixed order (strided per thread, then a
+// tree); also trace[t * n_imgs + i] when trace is not null.  One workgroup per
+// image.
 __global__ __launch_bounds__(kGroupThreads) void k_amp_alpha(const ImgDev* __restrict__ imgs,
-                                                            const float* __restrict__ b,
-                                                            const float* __restrict__ xp,
-                                                            const float* __restrict__ x,
+                                                            const double* __restrict__ csum,
                                                             const float* __restrict__ eps, float scale,
                                                             float* __restrict__ alpha, float* __restrict__ trace,
                                                             int n_imgs, int t) {
   __shared__ double sh[kGroupThreads];
   const ImgDev im = imgs[blockIdx.x];
-  const int64_t n = (int64_t)im.Hc * im.Wc;
+  const int64_t c0 = im.out_off >> kPixChunkShift, nc = ((int64_t)im.Hc * im.Wc) >> kPixChunkShift;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kGroupThreads) {
-    const int64_t p = im.out_off + i;
-    s += (double)b[p] * ((double)xp[p] - (double)x[p]);
-  }
+  for (int64_t i = threadIdx.x; i < nc; i += kGroupThreads) s += csum[c0 + i];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = kGroupThreads / 2; w > 0; w >>= 1) {
