@@ -287,6 +287,42 @@ int abcs_cnn_train_step(const abcs_plan* plan, float* d_params, float* d_adam_m,
 int abcs_denoise(const abcs_plan* plan, int denoiser, const void* d_params, const float* d_in,
                  const float* d_sigma, float* d_out, void* d_ws, size_t ws_bytes, void* stream);
 
+/* Full-sensing bounds (Section IV; Section V-C).  Every DCT coefficient of
+ * every block is measured and M = floor(C_R N) of them (N = H'W', C_R the
+ * image's subrate) are kept; the image's method field is not used.
+ *   ABCS_THI: the M coefficients of largest magnitude over the whole image
+ *             (one threshold per image), the best any adaptive 2-D DCT
+ *             scheme with M coefficients can do in error energy;
+ *   ABCS_THB: the floor(M / n_B) largest of every block (one threshold per
+ *             block, the same count in each).
+ * Magnitudes are compared on float64 coefficients computed in the fixed
+ * order T[r][v] = sum_j X[r][j] D[v][j], C[u][v] = sum_r D[u][r] T[r][v]
+ * (ascending indices, no fused multiply-add), so the kept set is exactly that
+ * definition's.  Ties in magnitude go to the lower block index (raster
+ * order), then the lower zigzag rank.
+ * d_px:  pixels as for abcs_budget (px_bytes >= the plan's extent).
+ * d_m:   out, int32[blocks] (plan block order): coefficients kept per block.
+ * d_out: out, nullable, float[pixels] (plan layout, 16-byte aligned): inverse
+ *        DCT of the kept coefficients, the others zero (float32 transform).
+ * d_ws:  abcs_threshold_workspace_bytes(plan) bytes (12 per pixel and a few
+ *        per block and image), 256-byte aligned; its contents on entry do not
+ *        matter.
+ * Errors: EINVAL (unknown rule, null or misaligned buffer), ENOSPACE (pixel
+ * buffer or workspace too small), EUNSUPPORTED (an image of 2^29 pixels or
+ * more), EHIP.  Allocates device tables on the first call with a plan. */
+typedef enum abcs_threshold_rule { ABCS_THI = 1, ABCS_THB = 2 } abcs_threshold_rule;
+size_t abcs_threshold_workspace_bytes(const abcs_plan* plan);
+int abcs_threshold(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, int rule, int32_t* d_m,
+                   float* d_out, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Pearson's correlation rho between two per-block counts over the blocks of
+ * each image (Table 2 correlates THI's m_i with the budgets an adaptive rule
+ * estimates).  d_m, d_m_hat: int32[blocks]; d_rho: out, double[n], NaN for an
+ * image where either count is constant.  Computed from exact integer moments.
+ * Errors: EINVAL (null or misaligned buffer), EHIP. */
+int abcs_budget_correlation(const abcs_plan* plan, const int32_t* d_m, const int32_t* d_m_hat, double* d_rho,
+                            void* stream);
+
 /* Host copy of the float64 orthonormal DCT-II basis the library uses,
  * D[u*B + j] = s_u cos((2j+1) u pi / (2B)), for checking.  B in {8, 16, 32}. */
 int abcs_dct_basis(int block, double* h_out);

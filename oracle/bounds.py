@@ -53,8 +53,10 @@ def _decode(coefs, keep, img, block):
 
 
 def total_measurements(img, block, subrate):
+    """(M, n_B) with M = floor(C_R N), N = H'W' (as every other rule)."""
     Hc, Wc, _, _, nB = abcs.geometry(img.shape[0], img.shape[1], block)
-    return int(math.floor(subrate * Hc * Wc)), nB
+    N = Hc * Wc
+    return int(math.floor(subrate * N)), nB
 
 
 def thi(img, block, subrate):

@@ -10,4 +10,5 @@ from .api import (ZZ, BBV, DD, Plan, AbcsError, budget, sense, reconstruct,  # n
                   dct_basis, METHODS, ida_refine, ida_iterate, ida_workspace_bytes, DENOISERS,
                   denoise, denoise_workspace_bytes, cnn_param_count, cnn_train_step,
                   cnn_train_workspace_bytes, IdaGraph, PRECISIONS,
-                  amp_refine, amp_workspace_bytes, ALGORITHMS)
+                  amp_refine, amp_workspace_bytes, ALGORITHMS, threshold,
+                  threshold_workspace_bytes, budget_correlation, RULES)

@@ -14,6 +14,7 @@ EXPORTS = [
     "ida_workspace_bytes", "ida_refine", "ida_iterate", "abcs_denoise_workspace_bytes", "abcs_denoise",
     "abcs_cnn_param_count", "abcs_cnn_train_workspace_bytes", "abcs_cnn_train_step",
     "ida_graph_create", "ida_graph_launch", "ida_graph_destroy", "amp_workspace_bytes", "amp_refine",
+    "abcs_threshold_workspace_bytes", "abcs_threshold", "abcs_budget_correlation",
 ]
 
 
@@ -80,12 +81,16 @@ def lib():
     L.amp_workspace_bytes.argtypes = [vp, i32]
     L.amp_workspace_bytes.restype = sz
     L.amp_refine.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.abcs_threshold_workspace_bytes.argtypes = [vp]
+    L.abcs_threshold_workspace_bytes.restype = sz
+    L.abcs_threshold.argtypes = [vp, vp, i64, i32, vp, vp, vp, sz, vp]
+    L.abcs_budget_correlation.argtypes = [vp, vp, vp, vp, vp]
     L.ida_graph_destroy.argtypes = [vp]
     L.ida_graph_destroy.restype = None
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("abcs_plan_destroy", "abcs_last_error", "ida_workspace_bytes", "ida_graph_destroy",
-                        "amp_workspace_bytes",
+                        "amp_workspace_bytes", "abcs_threshold_workspace_bytes",
                         "abcs_denoise_workspace_bytes", "abcs_cnn_param_count",
                         "abcs_cnn_train_workspace_bytes"):
             f.restype = ctypes.c_int

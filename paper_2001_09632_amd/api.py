@@ -213,6 +213,28 @@ def cnn_train_step(plan, params, adam_m, adam_v, step, lr, x_in, sigma, target, 
                                     _ptr(workspace), ws_bytes, _stream(stream)))
 
 
+THI, THB = 1, 2
+RULES = {"thi": THI, "thb": THB}
+
+
+def threshold_workspace_bytes(plan):
+    return int(lib().abcs_threshold_workspace_bytes(plan.handle))
+
+
+def threshold(plan, px, m, out=None, rule="thi", workspace=None, stream=None):
+    """abcs_threshold: full-sensing bound THI ("thi") or THB ("thb"); px uint8
+    pixels, m int32[blocks] (kept per block), out float32[pixels] or None."""
+    r = RULES[rule] if isinstance(rule, str) else int(rule)
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().abcs_threshold(plan.handle, _ptr(px), px.numel() * px.element_size(), r, _ptr(m), _ptr(out), _ptr(workspace),
+                               ws_bytes, _stream(stream)))
+
+
+def budget_correlation(plan, m, m_hat, rho, stream=None):
+    """abcs_budget_correlation: rho float64[n] <- Pearson(m, m_hat) per image."""
+    check(lib().abcs_budget_correlation(plan.handle, _ptr(m), _ptr(m_hat), _ptr(rho), _stream(stream)))
+
+
 def dct_basis(block):
     """Host float64 DCT-II basis used by the library (B x B nested list)."""
     buf = (ctypes.c_double * (block * block))()

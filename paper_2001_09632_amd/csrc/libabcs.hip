@@ -9,4 +9,5 @@
 #include "bm3d_kernels.hpp"
 #include "cnn_kernels.hpp"
 #include "generic_kernels.hpp"
+#include "threshold_kernels.hpp"
 #include "api.cpp.inc"
