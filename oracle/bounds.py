@@ -18,7 +18,9 @@ Readings (the formal definitions are in the paper's supplementary material,
 which is not available): ties in magnitude go to the lower block index, then
 the lower zigzag rank; the decoded image is the inverse DCT of the kept
 coefficients (the others zero).  rho is Pearson's correlation between THI's
-m_i and an estimator's per-block budget k_i.
+m_i and an estimator's per-block budget k_i, and p the probability of the
+null hypothesis rho = 0 (two-sided Student t test, the usual test for a
+correlation coefficient; the paper reports p below 1e-4 without naming it).
 
 Parity: pinned by tests/test_oracle_bounds.py: exact recovery at C_R = 1,
 error energy = sum of dropped c^2, THI <= THB <= L-DCT-ZZ in error energy,
@@ -82,6 +84,21 @@ def thb(img, block, subrate):
         order = np.argsort(-np.abs(coefs[i]), kind="stable")
         keep[i, order[:k]] = True
     return keep, _decode(coefs, keep, img, block)
+
+
+def pearson_p(rho, n):
+    """Two-sided p-value of the null hypothesis rho = 0 for n pairs: the
+    Student t statistic t = rho sqrt((n-2)/(1-rho^2)) with n-2 degrees of
+    freedom, P(|T| >= |t|) = I_x((n-2)/2, 1/2) with x = 1 - rho^2
+    (regularised incomplete beta function)."""
+    from scipy.special import betainc
+    if not np.isfinite(rho) or n < 3:
+        return float("nan")
+    nu = n - 2
+    x = (1.0 - rho) * (1.0 + rho)
+    if x <= 0.0:
+        return 0.0
+    return float(betainc(nu / 2.0, 0.5, x))
 
 
 def pearson(a, b):

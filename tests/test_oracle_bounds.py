@@ -66,3 +66,22 @@ def test_pearson_special_cases():
     rng = np.random.default_rng(0)
     x, y = rng.standard_normal(50), rng.standard_normal(50)
     assert bounds.pearson(x, y) == pytest.approx(float(np.corrcoef(x, y)[0, 1]), abs=1e-12)
+
+
+def test_pearson_p_closed_forms_and_library():
+    # n = 3: t has 1 degree of freedom (Cauchy): p = 1 - (2/pi) atan|t|
+    # n = 4: 2 degrees of freedom: p = 1 - |t| / sqrt(2 + t^2)
+    for rho in (0.1, 0.5, -0.7, 0.95):
+        t1 = abs(rho) * np.sqrt(1.0 / (1 - rho * rho))
+        assert bounds.pearson_p(rho, 3) == pytest.approx(1 - 2 / np.pi * np.arctan(t1), rel=1e-12)
+        t2 = abs(rho) * np.sqrt(2.0 / (1 - rho * rho))
+        assert bounds.pearson_p(rho, 4) == pytest.approx(1 - t2 / np.sqrt(2 + t2 * t2), rel=1e-12)
+    from scipy.stats import pearsonr
+    rng = np.random.default_rng(3)
+    for n in (10, 57, 400):
+        x = rng.standard_normal(n)
+        y = 0.3 * x + rng.standard_normal(n)
+        r, p = pearsonr(x, y)
+        assert bounds.pearson(x, y) == pytest.approx(r, abs=1e-12)
+        assert bounds.pearson_p(bounds.pearson(x, y), n) == pytest.approx(p, rel=1e-9)
+    assert bounds.pearson_p(1.0, 10) == 0.0 and np.isnan(bounds.pearson_p(float("nan"), 10))
