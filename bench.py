@@ -324,6 +324,54 @@ def stream_section(dev, n_requests=1000, load=0.5):
                                       "p99": round(float(np.percentile(lat, 99)), 3)}}}
 
 
+def bounds_section(dev, plan, px, k, out, images):
+    """Full-sensing bounds on the step's plan (Section IV, Section V-C): time
+    of THI and THB per call over all encodings, mean PSNR per C_R of THI, THB
+    and the adaptive decodings of the step, and the correlation of THI's
+    per-block counts with the BBV / DD budgets (the quantity of Table 2),
+    averaged over the images, with the largest p-value of rho = 0."""
+    import torch
+    import paper_2001_09632_amd as g
+    n_img = len(SEEDS)
+    ws = torch.empty(g.threshold_workspace_bytes(plan), dtype=torch.uint8, device=dev)
+    m = {r: torch.empty(plan.blocks, dtype=torch.int32, device=dev) for r in ("thi", "thb")}
+    dec = torch.empty(plan.pixels, dtype=torch.float32, device=dev)
+    rho = torch.empty(plan.n, dtype=torch.float64, device=dev)
+    pval = torch.empty(plan.n, dtype=torch.float64, device=dev)
+    ref = torch.from_numpy(images).to(dev).float()
+
+    def psnr(buf):
+        x = buf.view(len(METHODS), len(SUBRATES), n_img, H, W)
+        mse = ((x - ref[None, None]) ** 2).mean(dim=(3, 4))
+        return (10.0 * torch.log10(255.0 ** 2 / mse)).mean(dim=2)  # (method, C_R)
+
+    res = {"encodings": plan.n, "pixels": plan.pixels}
+    table = {"bbv": psnr(out)[0].tolist(), "dd": psnr(out)[1].tolist()}
+    for r in ("thi", "thb"):
+        g.threshold(plan, px, m[r], dec, rule=r, workspace=ws)
+        torch.cuda.synchronize()
+        table[r] = psnr(dec)[0].tolist()  # the same for both halves of the plan
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        for _ in range(3):
+            g.threshold(plan, px, m[r], dec, rule=r, workspace=ws)
+        e[1].record()
+        torch.cuda.synchronize()
+        ms = e[0].elapsed_time(e[1]) / 3
+        res[r + "_ms"] = round(ms, 3)
+        res[r + "_mpix_s"] = round(plan.pixels / (ms * 1e-3) / 1e6, 1)
+    g.budget_correlation(plan, m["thi"], k, rho, pval)
+    r = rho.view(len(METHODS), len(SUBRATES), n_img).nanmean(dim=2).tolist()
+    pmax = pval.view(len(METHODS), len(SUBRATES), n_img).amax(dim=2).tolist()
+    res["psnr_db_by_cr"] = {name: {str(cr): round(v, 3) for cr, v in zip(SUBRATES, vals)}
+                            for name, vals in table.items()}
+    res["rho_thi_vs_budget_by_cr"] = {meth: {str(cr): round(v, 4) for cr, v in zip(SUBRATES, r[i])}
+                                      for i, meth in enumerate(METHODS)}
+    res["p_value_max_by_cr"] = {meth: {str(cr): float("%.3g" % v) for cr, v in zip(SUBRATES, pmax[i])}
+                                for i, meth in enumerate(METHODS)}
+    return res
+
+
 def cpu_baseline(images, n_images, deadline_s=30.0):
     """The FP64 oracle (budget + sensing + decoding) on the first n_images of
     the batch at every (estimator, subrate) pair; single-threaded numpy."""
@@ -355,6 +403,7 @@ def main():
     ap.add_argument("--no-stream", action="store_true", help="skip the mixed request-stream section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ida", action="store_true")
+    ap.add_argument("--no-bounds", action="store_true", help="skip the THI / THB bounds section")
     ap.add_argument("--cnn-weights", default=os.path.join(ROOT, "paper_2001_09632_amd", "weights", "ida_cnn.npy"))
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a device-to-device copy of this many MiB (5 times) and exit; "
@@ -456,6 +505,11 @@ def main():
                       "max_abs_dy_vs_fp32": round(float((y_m - y32).abs().max()), 5),
                       "max_abs_dpx_vs_fp32": round(float((out_m - out32).abs().max()), 5)}
 
+    bounds = None
+    if not args.no_bounds:
+        log("bounds")
+        bounds = bounds_section(dev, plan, px, k, out32, images)
+
     ida = None
     if not args.no_ida:
         log("ida")
@@ -492,6 +546,7 @@ def main():
         "precision_modes": prec,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "bounds": bounds,
         "ida": ida,
         "stream": stream,
     }

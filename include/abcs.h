@@ -304,9 +304,9 @@ int abcs_denoise(const abcs_plan* plan, int denoiser, const void* d_params, cons
  * d_m:   out, int32[blocks] (plan block order): coefficients kept per block.
  * d_out: out, nullable, float[pixels] (plan layout, 16-byte aligned): inverse
  *        DCT of the kept coefficients, the others zero (float32 transform).
- * d_ws:  abcs_threshold_workspace_bytes(plan) bytes (12 per pixel and a few
- *        per block and image), 256-byte aligned; its contents on entry do not
- *        matter.
+ * d_ws:  abcs_threshold_workspace_bytes(plan) bytes (12 per pixel, 4 per
+ *        block and about 16 KiB per image), 256-byte aligned; its contents on
+ *        entry do not matter.
  * Errors: EINVAL (unknown rule, null or misaligned buffer), ENOSPACE (pixel
  * buffer or workspace too small), EUNSUPPORTED (an image of 2^29 pixels or
  * more), EHIP.  Allocates device tables on the first call with a plan. */
@@ -317,11 +317,16 @@ int abcs_threshold(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes,
 
 /* Pearson's correlation rho between two per-block counts over the blocks of
  * each image (Table 2 correlates THI's m_i with the budgets an adaptive rule
- * estimates).  d_m, d_m_hat: int32[blocks]; d_rho: out, double[n], NaN for an
- * image where either count is constant.  Computed from exact integer moments.
+ * estimates), and the probability p of the null hypothesis rho = 0 that
+ * Section V-C reports: two-sided Student t test, t = rho sqrt(nu / (1 -
+ * rho^2)), nu = n_B - 2, p = I_{1-rho^2}(nu/2, 1/2) (regularised incomplete
+ * beta function, continued fraction; relative error ~1e-13).
+ * d_m, d_m_hat: int32[blocks]; d_rho: out, double[n], NaN for an image where
+ * either count is constant; d_p: out, nullable, double[n] (NaN where rho is
+ * or n_B < 3).  rho is computed from exact integer moments.
  * Errors: EINVAL (null or misaligned buffer), EHIP. */
 int abcs_budget_correlation(const abcs_plan* plan, const int32_t* d_m, const int32_t* d_m_hat, double* d_rho,
-                            void* stream);
+                            double* d_p, void* stream);
 
 /* Host copy of the float64 orthonormal DCT-II basis the library uses,
  * D[u*B + j] = s_u cos((2j+1) u pi / (2B)), for checking.  B in {8, 16, 32}. */

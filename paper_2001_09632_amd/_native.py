@@ -84,7 +84,7 @@ def lib():
     L.abcs_threshold_workspace_bytes.argtypes = [vp]
     L.abcs_threshold_workspace_bytes.restype = sz
     L.abcs_threshold.argtypes = [vp, vp, i64, i32, vp, vp, vp, sz, vp]
-    L.abcs_budget_correlation.argtypes = [vp, vp, vp, vp, vp]
+    L.abcs_budget_correlation.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ida_graph_destroy.argtypes = [vp]
     L.ida_graph_destroy.restype = None
     for name in EXPORTS:

@@ -230,9 +230,10 @@ def threshold(plan, px, m, out=None, rule="thi", workspace=None, stream=None):
                                ws_bytes, _stream(stream)))
 
 
-def budget_correlation(plan, m, m_hat, rho, stream=None):
-    """abcs_budget_correlation: rho float64[n] <- Pearson(m, m_hat) per image."""
-    check(lib().abcs_budget_correlation(plan.handle, _ptr(m), _ptr(m_hat), _ptr(rho), _stream(stream)))
+def budget_correlation(plan, m, m_hat, rho, p=None, stream=None):
+    """abcs_budget_correlation: rho float64[n] <- Pearson(m, m_hat) per image,
+    p float64[n] (or None) <- two-sided p-value of rho = 0."""
+    check(lib().abcs_budget_correlation(plan.handle, _ptr(m), _ptr(m_hat), _ptr(rho), _ptr(p), _stream(stream)))
 
 
 def dct_basis(block):

@@ -128,35 +128,44 @@ def test_thi_ties_across_blocks():
         _check(run, len(crs) + j, flat, 16, cr)
 
 
-def test_budget_correlation_matches_oracle():
+@pytest.mark.parametrize("size", [256, 64])
+def test_budget_correlation_matches_oracle(size):
+    """rho and its p-value per image (64 x 64: 16 blocks, p of order 1e-3
+    .. 1; 256 x 256: 256 blocks, p down to ~1e-100)."""
     import torch
     import paper_2001_09632_amd as g
     from gpu_util import Run
-    imgs = [synth.synth_image(970 + i, 256, 256) for i in range(3)]
+    imgs = [synth.synth_image(970 + i + size, size, size) for i in range(3)]
     px, d = pack_images(imgs)
     crs = (0.1, 0.3, 0.5)
     entries, cases = [], []
     for i in range(3):
         for cr in crs:
             for meth in ("bbv", "dd", "zz"):
+                try:
+                    orc.budget_scalars(size, size, 16, cr, orc.METHOD_NAMES[meth])
+                except orc.DomainError:
+                    continue
                 entries.append(dict(d[i], block=16, subrate=cr, method=meth))
                 cases.append((i, cr, meth))
     est = Run(px, entries).budget()
     bnd = BoundRun(px, entries)
     bnd.run(rules=("thi",), decode=False)
     rho = torch.full((len(entries),), -7.0, dtype=torch.float64, device=device())
-    g.budget_correlation(bnd.plan, bnd.m["thi"], est.k, rho)
+    pv = torch.full((len(entries),), -7.0, dtype=torch.float64, device=device())
+    g.budget_correlation(bnd.plan, bnd.m["thi"], est.k, rho, pv)
     est.fetch()
-    rho_h = rho.cpu().numpy()
+    rho_h, p_h = rho.cpu().numpy(), pv.cpu().numpy()
     for j, (i, cr, meth) in enumerate(cases):
         m_ref, _, _ = ob.thi(imgs[i], 16, cr)
         k_ref, _ = orc.budget(imgs[i], 16, cr, orc.METHOD_NAMES[meth])
         want = ob.pearson(m_ref, k_ref)
-        if meth == "zz":
-            assert np.isnan(rho_h[j]) and np.isnan(want)
-        else:
-            assert abs(rho_h[j] - want) < 1e-9, f"rho {rho_h[j]} vs {want} ({meth}, C_R {cr})"
-            assert -1.0 <= want <= 1.0
+        if np.isnan(want):
+            assert np.isnan(rho_h[j]) and np.isnan(p_h[j]), f"constant budget must give NaN ({meth})"
+            continue
+        assert abs(rho_h[j] - want) < 1e-9, f"rho {rho_h[j]} vs {want} ({meth}, C_R {cr})"
+        p_ref = ob.pearson_p(want, m_ref.size)
+        assert abs(p_h[j] - p_ref) <= 1e-9 * p_ref + 1e-300, f"p {p_h[j]} vs {p_ref} ({meth}, C_R {cr})"
 
 
 def test_bounds_full_size_512():
