@@ -144,6 +144,18 @@ __device__ __forceinline__ void thb_keep(const uint32_t (&hv)[PER], const uint32
 
 constexpr int kRuleTHI = 0, kRuleTHB = 1;
 
+// Register tiling of the float64 transform: each lane computes an R x R
+// patch of T and of C, so one LDS load feeds R multiply-adds; a block takes
+// LPB lanes and a wave BPW blocks at once.
+template <int B>
+struct ThrGeom {
+  static constexpr int R = B == 8 ? 2 : 4;
+  static constexpr int NN = B * B, P = B + 1;
+  static constexpr int LPB = NN / (R * R);  // lanes per block
+  static constexpr int BPW = 64 / LPB;      // blocks per wave
+  static constexpr int SLOTS = kWavesPerGroup * BPW;
+};
+
 // Every coefficient of the tile's blocks in float64: C[u][v] = sum_r D[u][r]
 // T[r][v], T[r][v] = sum_j X[r][j] D[v][j], sums in ascending index order,
 // every product and sum rounded on its own.
@@ -157,17 +169,15 @@ __global__ __launch_bounds__(kGroupThreads) void k_thr_coefs(const ImgDev* __res
                                                             const int64_t* __restrict__ m_total,
                                                             float* __restrict__ yfull, int32_t* __restrict__ m) {
 #pragma clang fp contract(off)
-  constexpr int P = B + 1, NN = B * B, PER = NN / 64;
-  __shared__ double sD[NN];      // D[u][j] at u B + j
-  __shared__ double sDt[NN];     // D[v][j] at j B + v
+  using G = ThrGeom<B>;
+  constexpr int R = G::R, NN = G::NN, P = G::P, PER = NN / 64;
+  __shared__ __align__(16) double sDt[NN];   // D[a][b] at b B + a
   __shared__ uint16_t srank[NN];
-  __shared__ float sX[kWavesPerGroup][B * P];   // pixels, then high words by rank
-  __shared__ double sT[kWavesPerGroup][B * P];
-  __shared__ uint32_t sLo[kWavesPerGroup][NN];
+  __shared__ float sX[G::SLOTS][B * P];      // pixels, then high words by rank
+  __shared__ __align__(16) double sT[G::SLOTS][NN];  // T[r][v] at r B + v, then low words
   if ((int)blockIdx.x >= ntiles) return;
   for (int t = threadIdx.x; t < NN; t += kGroupThreads) {
-    const double d = ThrTables<B>::Dd()[t];
-    sD[t] = d;
+    const double d = ThrTables<B>::Dd()[t];  // D[a][b] at a B + b
     sDt[(t % B) * B + t / B] = d;
     srank[t] = (uint16_t)ThrTables<B>::rank(t);
   }
@@ -175,58 +185,107 @@ __global__ __launch_bounds__(kGroupThreads) void k_thr_coefs(const ImgDev* __res
   const Tile tl = tiles[blockIdx.x];
   const ImgDev im = imgs[tl.img];
   const int w = wave_in_group(), lane = threadIdx.x & 63;
+  const int g = lane / G::LPB, li = lane % G::LPB;
+  const int a0 = R * (li / (B / R)), b0 = R * (li % (B / R));  // patch origin (row, column)
   const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, (B - 1) * im.pitch + B * tl.count);
-  float* X = sX[w];
-  uint32_t* H = reinterpret_cast<uint32_t*>(sX[w]);
-  double* T = sT[w];
-  uint32_t* Lo = sLo[w];
   const int kb = RULE == kRuleTHB ? (int)(m_total[tl.img] / im.nB) : 0;
-  for (int bb = w; bb < tl.count; bb += kWavesPerGroup) {
-    gen_load_pixels<B>(rp, im.pitch, bb, X);
+  for (int base_bb = 0; base_bb < tl.count; base_bb += G::SLOTS) {
+    const int first = base_bb + w * G::BPW;  // the wave's first block
+    if (first >= tl.count) break;
+    for (int q = 0; q < G::BPW; ++q)
+      if (first + q < tl.count) gen_load_pixels<B>(rp, im.pitch, first + q, sX[w * G::BPW + q]);
     wave_lds_sync();
-    for (int idx = lane; idx < NN; idx += 64) {
-      const int r = idx / B, v = idx - r * B;
-      double s = 0.0;
+    const int slot = w * G::BPW + g;
+    const bool active = first + g < tl.count;
+    float* X = sX[slot];
+    double* T = sT[slot];
+    double acc[R][R];
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[i][k] = 0.0;
       for (int j = 0; j < B; ++j) {
-        const double p = (double)X[r * P + j] * sDt[j * B + v];
-        s = s + p;
+        double x[R], d[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) x[i] = (double)X[(a0 + i) * P + j];
+#pragma unroll
+        for (int k = 0; k < R; ++k) d[k] = sDt[j * B + b0 + k];
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const double p = x[i] * d[k];
+            acc[i][k] = acc[i][k] + p;
+          }
       }
-      T[r * P + v] = s;
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int k = 0; k < R; ++k) T[(a0 + i) * B + b0 + k] = acc[i][k];
     }
     wave_lds_sync();
-    for (int idx = lane; idx < NN; idx += 64) {
-      const int u = idx / B, v = idx - u * B;
-      double s = 0.0;
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[i][k] = 0.0;
       for (int r = 0; r < B; ++r) {
-        const double p = sD[u * B + r] * T[r * P + v];
-        s = s + p;
+        double du[R], t[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) du[i] = sDt[r * B + a0 + i];
+#pragma unroll
+        for (int k = 0; k < R; ++k) t[k] = T[r * B + b0 + k];
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const double p = du[i] * t[k];
+            acc[i][k] = acc[i][k] + p;
+          }
       }
-      const uint64_t bits = (uint64_t)__double_as_longlong(s);
-      const int z = srank[idx];
-      H[z] = (uint32_t)(bits >> 32);
-      Lo[z] = (uint32_t)bits;
+    }
+    // every lane of the wave has read T before any lane overwrites it
+    wave_lds_sync();
+    if (active) {
+      uint32_t* H = reinterpret_cast<uint32_t*>(X);
+      uint32_t* Lo = reinterpret_cast<uint32_t*>(T);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const uint64_t bits = (uint64_t)__double_as_longlong(acc[i][k]);
+          const int z = srank[(a0 + i) * B + b0 + k];
+          H[z] = (uint32_t)(bits >> 32);
+          Lo[z] = (uint32_t)bits;
+        }
     }
     wave_lds_sync();
-    const int64_t dst = im.out_off + (int64_t)(tl.first + bb) * NN;
-    if (RULE == kRuleTHI) {
+    for (int q = 0; q < G::BPW && first + q < tl.count; ++q) {
+      const int bb = first + q;
+      const uint32_t* H = reinterpret_cast<const uint32_t*>(sX[w * G::BPW + q]);
+      const uint32_t* Lo = reinterpret_cast<const uint32_t*>(sT[w * G::BPW + q]);
+      const int64_t dst = im.out_off + (int64_t)(tl.first + bb) * NN;
+      if (RULE == kRuleTHI) {
 #pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        khi[dst + 64 * j + lane] = H[64 * j + lane];
-        klo[dst + 64 * j + lane] = Lo[64 * j + lane];
+        for (int j = 0; j < PER; ++j) {
+          khi[dst + 64 * j + lane] = H[64 * j + lane];
+          klo[dst + 64 * j + lane] = Lo[64 * j + lane];
+        }
+      } else {
+        uint32_t hv[PER], lv[PER];
+        bool keep[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          hv[j] = H[64 * j + lane] & 0x7fffffffu;
+          lv[j] = Lo[64 * j + lane];
+        }
+        thb_keep<PER>(hv, lv, kb, keep);
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+          yfull[dst + 64 * j + lane] = keep[j] ? thr_value(H[64 * j + lane], lv[j]) : 0.f;
+        if (lane == 0) m[im.blk_off + tl.first + bb] = kb;
       }
-    } else {
-      uint32_t hv[PER], lv[PER];
-      bool keep[PER];
-#pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        hv[j] = H[64 * j + lane] & 0x7fffffffu;
-        lv[j] = Lo[64 * j + lane];
-      }
-      thb_keep<PER>(hv, lv, kb, keep);
-#pragma unroll
-      for (int j = 0; j < PER; ++j)
-        yfull[dst + 64 * j + lane] = keep[j] ? thr_value(H[64 * j + lane], lv[j]) : 0.f;
-      if (lane == 0) m[im.blk_off + tl.first + bb] = kb;
     }
     wave_lds_sync();
   }
