@@ -11,6 +11,8 @@ of every floating-point sum is fixed:
   budget_scalars   N, M, C_F, L, X0, n_S, M_BBV, m1, T, pool, cap
                    (eqs 16-18, 21; Alg 2 step 2; Table 1)
   dct_matrix       orthonormal DCT-II basis D (B x B)
+  walsh_matrix     orthonormal Walsh-Hadamard basis in sequency order (the
+                   alternative sensing transform named in Section IV)
   zigzag           JPEG zigzag scan order of a B x B block (Section IV)
   block_dct        C = D X D^T per block, fixed summation order
   block_idct       X = D^T C D per block
@@ -163,6 +165,35 @@ def dct_matrix(block):
     return D
 
 
+def walsh_matrix(block):
+    """Orthonormal Walsh-Hadamard basis in sequency order: W[s, j] = +-1/sqrt(B)
+    with row s the Walsh function of s sign changes (first entry positive).
+
+    Built from Sylvester's natural-order Hadamard matrix H[k, j] =
+    (-1)^popcount(k & j) by sorting its rows by their number of sign changes,
+    so that the zigzag scan runs from low to high sequency as it runs from low
+    to high frequency for the DCT.
+    """
+    B = int(block)
+    if B < 1 or B & (B - 1):
+        raise ValueError("Walsh-Hadamard order must be a power of two")
+    H = np.array([[(-1.0) ** bin(k & j).count("1") for j in range(B)] for k in range(B)])
+    changes = [int(np.count_nonzero(H[k, 1:] != H[k, :-1])) for k in range(B)]
+    return H[np.argsort(changes, kind="stable")] / math.sqrt(B)
+
+
+TRANSFORMS = ("dct", "wht")
+
+
+def basis(block, transform="dct"):
+    """The sensing transform's B x B basis: DCT-II (default) or Walsh-Hadamard."""
+    if transform == "dct":
+        return dct_matrix(block)
+    if transform == "wht":
+        return walsh_matrix(block)
+    raise ValueError(f"unknown transform {transform!r}")
+
+
 def zigzag(block):
     """JPEG zigzag scan of a B x B block as a list of (row, col) pairs.
 
@@ -266,10 +297,11 @@ def bbv_stat(img, block, L, X0, nS):
     return out
 
 
-def dd_stat(img, block, m1, T):
-    """n_i = #{z < m1 : |C_i[zigzag[z]]| > T}, C_i from block_dct (float64)."""
+def dd_stat(img, block, m1, T, transform="dct"):
+    """n_i = #{z < m1 : |C_i[zigzag[z]]| > T}, C_i from block_dct (float64)
+    with the sensing transform's basis."""
     B = int(block)
-    D = dct_matrix(B)
+    D = basis(B, transform)
     C = block_dct(to_blocks(img, B), D)
     zz = zigzag(B)[:m1]
     if m1 == 0:
@@ -327,10 +359,10 @@ def apportion(pool, weights, cap):
         return a
 
 
-def budget(img, block, subrate, method):
+def budget(img, block, subrate, method, transform="dct"):
     """Per-block coefficient counts k (int64, raster order) and the phase-1
     statistic (BBV_i or n_i; zeros for ZZ) for one image (Alg 1/2 steps 1-4).
-    """
+    DD's phase-1 coefficients are those of the sensing transform."""
     s = budget_scalars(img.shape[0], img.shape[1], block, subrate, method)
     nB = s["nB"]
     if s["mode"] == ZZ:
@@ -338,7 +370,7 @@ def budget(img, block, subrate, method):
     if s["mode"] == BBV:
         w = bbv_stat(img, block, s["L"], s["X0"], s["nS"])
         return apportion(s["pool"], w, s["cap"]), w
-    w = dd_stat(img, block, s["m1"], s["T"])
+    w = dd_stat(img, block, s["m1"], s["T"], transform)
     return s["m1"] + apportion(s["pool"], w, s["cap"]), w
 
 
@@ -358,11 +390,11 @@ def _zigzag_index(block):
     return np.array([p[0] for p in zz]), np.array([p[1] for p in zz])
 
 
-def sense_op(x_img, block, k):
-    """A x: for each block the first k_i zigzag DCT coefficients, packed
+def sense_op(x_img, block, k, transform="dct"):
+    """A x: for each block the first k_i zigzag transform coefficients, packed
     block after block (raster order), zigzag order within a block."""
     B = int(block)
-    C = block_dct(to_blocks(x_img, B), dct_matrix(B))
+    C = block_dct(to_blocks(x_img, B), basis(B, transform))
     rows, cols = _zigzag_index(B)
     czz = C[:, rows, cols]                       # (n_B, B^2) in zigzag order
     k = np.asarray(k, dtype=np.int64)
@@ -370,9 +402,9 @@ def sense_op(x_img, block, k):
     return czz[keep]
 
 
-def sense_adjoint(z, block, k, nby, nbx):
+def sense_adjoint(z, block, k, nby, nbx, transform="dct"):
     """A* z: put each block's coefficients back at their zigzag positions,
-    zero elsewhere, and apply the inverse block DCT."""
+    zero elsewhere, and apply the inverse block transform."""
     B = int(block)
     rows, cols = _zigzag_index(B)
     k = np.asarray(k, dtype=np.int64)
@@ -381,22 +413,22 @@ def sense_adjoint(z, block, k, nby, nbx):
     czz[keep] = np.asarray(z, dtype=np.float64)
     C = np.zeros((k.size, B, B), dtype=np.float64)
     C[:, rows, cols] = czz
-    return from_blocks(block_idct(C, dct_matrix(B)), nby, nbx)
+    return from_blocks(block_idct(C, basis(B, transform)), nby, nbx)
 
 
-def sense(img, block, k):
+def sense(img, block, k, transform="dct"):
     """Phase-2 measurement vector y (Alg 1 step 4, Alg 2 step 5): the first
-    k_i zigzag 2D-DCT coefficients of each block of the cropped image."""
-    return sense_op(np.asarray(img, dtype=np.float64), block, k)
+    k_i zigzag 2D-transform coefficients of each block of the cropped image."""
+    return sense_op(np.asarray(img, dtype=np.float64), block, k, transform)
 
 
-def reconstruct(y, block, k, height, width):
-    """Real-time decoder output I_o: zero-filled masked inverse 2D-DCT."""
+def reconstruct(y, block, k, height, width, transform="dct"):
+    """Real-time decoder output I_o: zero-filled masked inverse 2D transform."""
     _, _, nbx, nby, _ = geometry(height, width, block)
-    return sense_adjoint(np.asarray(y, dtype=np.float64), block, k, nby, nbx)
+    return sense_adjoint(np.asarray(y, dtype=np.float64), block, k, nby, nbx, transform)
 
 
-def encode(img, block, subrate, method):
+def encode(img, block, subrate, method, transform="dct"):
     """Budget + sensing for one image: returns (k, stat, y)."""
-    k, stat = budget(img, block, subrate, method)
-    return k, stat, sense(img, block, k)
+    k, stat = budget(img, block, subrate, method, transform)
+    return k, stat, sense(img, block, k, transform)

@@ -50,13 +50,14 @@ def identity_denoiser(v, sigma):
 
 
 def ida(y, k, block, height, width, iters, damping, denoiser=identity_denoiser,
-        trace=None):
+        trace=None, transform="dct"):
     """Run `iters` IDA iterations for one image.
 
     y       measurements (float, packed as abcs.sense produces them)
     k       per-block coefficient counts
     returns (x^T as a float64 (H', W') array, list of sigma^t)
     `trace`, if a list, receives (t, v^t, sigma^t) for every iteration.
+    `transform` is the sensing transform of A ("dct" or "wht").
     """
     Hc, Wc, nbx, nby, _ = abcs.geometry(height, width, block)
     y = np.asarray(y, dtype=np.float64)
@@ -66,10 +67,10 @@ def ida(y, k, block, height, width, iters, damping, denoiser=identity_denoiser,
     z_prev = np.zeros(m, dtype=np.float64)
     sigmas = []
     for t in range(int(iters)):
-        r = y - abcs.sense_op(x, block, k)
+        r = y - abcs.sense_op(x, block, k, transform)
         z = r + alpha * z_prev
         sigma = math.sqrt(float(np.sum(z * z)) / m) if m else 0.0
-        v = x + abcs.sense_adjoint(z, block, k, nby, nbx)
+        v = x + abcs.sense_adjoint(z, block, k, nby, nbx, transform)
         if trace is not None:
             trace.append((t, v.copy(), sigma))
         x = np.asarray(denoiser(v, sigma), dtype=np.float64)
@@ -79,7 +80,7 @@ def ida(y, k, block, height, width, iters, damping, denoiser=identity_denoiser,
 
 
 def amp(y, k, block, height, width, iters, damping, probe, denoiser=identity_denoiser,
-        algorithm="damp"):
+        algorithm="damp", transform="dct"):
     """Run `iters` iterations of D-AMP (algorithm "damp", eqs 13-15, 24) or
     DAMP-D ("damp-d", eq 27) for one image.
 
@@ -98,10 +99,10 @@ def amp(y, k, block, height, width, iters, damping, probe, denoiser=identity_den
     alpha = 0.0
     sigmas, alphas = [], []
     for t in range(int(iters)):
-        r = y - abcs.sense_op(x, block, k)
+        r = y - abcs.sense_op(x, block, k, transform)
         z = r + alpha * z_prev
         sigma = math.sqrt(float(np.sum(z * z)) / m) if m else 0.0
-        v = x + abcs.sense_adjoint(z, block, k, nby, nbx)
+        v = x + abcs.sense_adjoint(z, block, k, nby, nbx, transform)
         x_new = np.asarray(denoiser(v, sigma), dtype=np.float64)
         sigmas.append(sigma)
         alphas.append(alpha)
