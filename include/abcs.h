@@ -69,9 +69,19 @@ typedef enum abcs_denoiser {
   ABCS_DENOISE_CNN = 2       /* learned 8-layer 3x3 CNN (parameters passed)  */
 } abcs_denoiser;
 
-/* Arithmetic of the B = 16 block transforms in abcs_sense and
- * abcs_reconstruct (B = 8 and 32 always use float32 operands with float64
- * sums).  The 16-bit modes run on the matrix cores with float32 sums; the
+/* Sensing transform of an image (Section IV): the 2-D DCT-II, or the 2-D
+ * Walsh-Hadamard transform the paper names as the simpler alternative
+ * ({+1, -1} / sqrt(B) entries, rows in sequency order, so that the zigzag scan
+ * runs from low to high sequency).  DD's phase-1 coefficients are those of
+ * the image's transform. */
+typedef enum abcs_transform {
+  ABCS_DCT = 0,
+  ABCS_WHT = 1
+} abcs_transform;
+
+/* Arithmetic of the B = 16 DCT transforms in abcs_sense and
+ * abcs_reconstruct (B = 8 and 32, and Walsh-Hadamard images of every B,
+ * always use float32 operands with float64 sums).  The 16-bit modes run on the matrix cores with float32 sums; the
  * "x3" modes split each operand that is not exact in 16 bits into a high and a
  * low part and keep every product but low x low (about float32 accuracy); the
  * single-pass modes round the operands once.  Budgets (abcs_budget) never
@@ -95,7 +105,7 @@ typedef struct abcs_image {
   int32_t block;         /* B: 8, 16 or 32                                   */
   double subrate;        /* C_R in (0, 1]                                    */
   int32_t method;        /* abcs_method                                      */
-  int32_t reserved;      /* must be 0                                        */
+  int32_t transform;     /* abcs_transform (0: DCT)                          */
   int64_t pixel_offset;  /* byte offset of pixel (0,0) in the pixel buffer;
                             multiple of 4.  Several descriptors may name the
                             same pixels (e.g. one image at several C_R).      */
@@ -117,8 +127,9 @@ typedef struct abcs_plan abcs_plan; /* opaque */
  * that must be released with abcs_plan_destroy.
  * Errors: EINVAL (null pointer, n < 0, pitch/offset/alignment), EDOMAIN
  * (C_R outside (0,1], no whole block, M = 0, BBV with C_R > 0.5, BBV samples
- * exceeding M), EUNSUPPORTED (B not 8, 16 or 32), EHIP.  B = 16 runs on the
- * matrix cores; B = 8 and 32 run on the vector ALUs (same results and error
+ * exceeding M), EINVAL (unknown transform), EUNSUPPORTED (B not 8, 16 or
+ * 32), EHIP.  DCT images with B = 16 run on the matrix cores; B = 8 and 32
+ * and Walsh-Hadamard images run on the vector ALUs (same results and error
  * bars: budgets and index sets exact, DD statistics evaluated in float64). */
 int abcs_plan_create(const abcs_image* h_imgs, int n, abcs_plan** out);
 void abcs_plan_destroy(abcs_plan* plan);
@@ -309,7 +320,7 @@ int abcs_denoise(const abcs_plan* plan, int denoiser, const void* d_params, cons
  *        entry do not matter.
  * Errors: EINVAL (unknown rule, null or misaligned buffer), ENOSPACE (pixel
  * buffer or workspace too small), EUNSUPPORTED (an image of 2^29 pixels or
- * more), EHIP.  Allocates device tables on the first call with a plan. */
+ * more, or a Walsh-Hadamard image: the bounds are the DCT's), EHIP.  Allocates device tables on the first call with a plan. */
 typedef enum abcs_threshold_rule { ABCS_THI = 1, ABCS_THB = 2 } abcs_threshold_rule;
 size_t abcs_threshold_workspace_bytes(const abcs_plan* plan);
 int abcs_threshold(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, int rule, int32_t* d_m,

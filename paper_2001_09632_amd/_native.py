@@ -28,7 +28,7 @@ class ImageDesc(ctypes.Structure):
     _fields_ = [
         ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("row_pitch", ctypes.c_int32),
         ("block", ctypes.c_int32), ("subrate", ctypes.c_double), ("method", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("pixel_offset", ctypes.c_int64),
+        ("transform", ctypes.c_int32), ("pixel_offset", ctypes.c_int64),
         ("block_offset", ctypes.c_int64), ("meas_offset", ctypes.c_int64),
         ("out_offset", ctypes.c_int64), ("n_meas", ctypes.c_int64),
         ("cropped_height", ctypes.c_int32), ("cropped_width", ctypes.c_int32),

@@ -18,13 +18,17 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
+TRANSFORMS = {"dct": 0, "wht": 1}
+
+
 class Plan:
     """A validated batch of images (abcs_plan_create).
 
     images: iterable of dicts with keys height, width, block, subrate,
-    method (0/1/2 or 'zz'/'bbv'/'dd'), and optionally row_pitch (default
-    width rounded up to 4) and pixel_offset (default: images packed one after
-    the other).  Create it with the target device current.
+    method (0/1/2 or 'zz'/'bbv'/'dd'), and optionally transform ('dct'
+    (default) or 'wht', or 0/1), row_pitch (default width rounded up to 4)
+    and pixel_offset (default: images packed one after the other).  Create it
+    with the target device current.
     """
 
     def __init__(self, images):
@@ -42,7 +46,9 @@ class Plan:
                 offset = (offset + 3) // 4 * 4
             arr[i].height, arr[i].width, arr[i].row_pitch = int(d["height"]), int(d["width"]), pitch
             arr[i].block, arr[i].subrate, arr[i].method = int(d["block"]), float(d["subrate"]), m
-            arr[i].reserved, arr[i].pixel_offset = int(d.get("reserved", 0)), int(po)
+            xf = d.get("transform", "dct")
+            arr[i].transform = TRANSFORMS[xf] if isinstance(xf, str) else int(xf)
+            arr[i].pixel_offset = int(po)
         self._h = ctypes.c_void_p()
         check(lib().abcs_plan_create(arr, len(imgs), ctypes.byref(self._h)))
         self.n = len(imgs)

@@ -1,4 +1,5 @@
-// Block transforms for B = 8 and B = 32 on the vector ALUs: phase-1 DD
+// Block transforms on the vector ALUs (DCT with B = 8 and B = 32, and the
+// Walsh-Hadamard transform of Section IV with B = 8, 16, 32): phase-1 DD
 // statistic (in float64, in the fixed order of the definition), sensing,
 // masked inverse DCT and the IDA transform step.  A workgroup takes a tile of
 // up to 16 consecutive blocks of a block row; wavefront w handles blocks
@@ -26,20 +27,53 @@ __constant__ uint16_t c_zzrank8[64];
 __constant__ uint16_t c_zzpos8[64];
 __constant__ uint16_t c_zzrank32[1024];
 __constant__ uint16_t c_zzpos32[1024];
+// Orthonormal sequency-ordered Walsh-Hadamard bases W[s*B + j] (float32 and
+// float64), and 16-bit zigzag tables for B = 16.
+__constant__ float c_W8[64];
+__constant__ double c_W8d[64];
+__constant__ float c_W16[256];
+__constant__ double c_W16d[256];
+__constant__ float c_W32[1024];
+__constant__ double c_W32d[1024];
+__constant__ uint16_t c_zzrank16w[256];
+__constant__ uint16_t c_zzpos16[256];
 
-template <int B>
+constexpr int kXfDCT = 0, kXfWHT = 1;
+
+template <int B, int XF>
 struct GenTables;
 template <>
-struct GenTables<8> {
+struct GenTables<8, kXfDCT> {
   __device__ static const float* D() { return c_D8; }
   __device__ static const double* Dd() { return c_D8d; }
   __device__ static const uint16_t* rank() { return c_zzrank8; }
   __device__ static const uint16_t* pos() { return c_zzpos8; }
 };
 template <>
-struct GenTables<32> {
+struct GenTables<32, kXfDCT> {
   __device__ static const float* D() { return c_D32; }
   __device__ static const double* Dd() { return c_D32d; }
+  __device__ static const uint16_t* rank() { return c_zzrank32; }
+  __device__ static const uint16_t* pos() { return c_zzpos32; }
+};
+template <>
+struct GenTables<8, kXfWHT> {
+  __device__ static const float* D() { return c_W8; }
+  __device__ static const double* Dd() { return c_W8d; }
+  __device__ static const uint16_t* rank() { return c_zzrank8; }
+  __device__ static const uint16_t* pos() { return c_zzpos8; }
+};
+template <>
+struct GenTables<16, kXfWHT> {
+  __device__ static const float* D() { return c_W16; }
+  __device__ static const double* Dd() { return c_W16d; }
+  __device__ static const uint16_t* rank() { return c_zzrank16w; }
+  __device__ static const uint16_t* pos() { return c_zzpos16; }
+};
+template <>
+struct GenTables<32, kXfWHT> {
+  __device__ static const float* D() { return c_W32; }
+  __device__ static const double* Dd() { return c_W32d; }
   __device__ static const uint16_t* rank() { return c_zzrank32; }
   __device__ static const uint16_t* pos() { return c_zzpos32; }
 };
@@ -55,12 +89,12 @@ struct GenShared {
   float b[kWavesPerGroup][B * P];        // per wave: second pass / rank-ordered buffer
 };
 
-template <int B>
+template <int B, int XF>
 __device__ __forceinline__ void gen_load_tables(GenShared<B>& sh) {
   constexpr int P = B + 1;
   for (int t = threadIdx.x; t < B * B; t += kGroupThreads) {
-    sh.D[(t / B) * P + t % B] = GenTables<B>::D()[t];
-    sh.rank[t] = GenTables<B>::rank()[t];
+    sh.D[(t / B) * P + t % B] = GenTables<B, XF>::D()[t];
+    sh.rank[t] = GenTables<B, XF>::rank()[t];
   }
 }
 
@@ -151,7 +185,7 @@ __device__ __forceinline__ void gen_block_range(const ImgDev& im, const int32_t*
 // ascending), C[u][v] = sum_r D[u][r] T[r][v] (r ascending), every product
 // and sum rounded on its own; n_i = #{z < m1 : |C[zz(z)]| > T}.
 // ---------------------------------------------------------------------------
-template <int B>
+template <int B, int XF>
 __global__ __launch_bounds__(kGroupThreads) void k_gen_dd_stats(const ImgDev* __restrict__ imgs,
                                                                const Tile* __restrict__ tiles, int ntiles,
                                                                const uint8_t* __restrict__ px,
@@ -164,8 +198,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_dd_stats(const ImgDev* __
   __shared__ double sT[kWavesPerGroup][B * P];
   if ((int)blockIdx.x >= ntiles) return;
   for (int t = threadIdx.x; t < B * B; t += kGroupThreads) {
-    sDd[t] = GenTables<B>::Dd()[t];
-    spos[t] = GenTables<B>::pos()[t];
+    sDd[t] = GenTables<B, XF>::Dd()[t];
+    spos[t] = GenTables<B, XF>::pos()[t];
   }
   __syncthreads();
   const Tile tl = tiles[blockIdx.x];
@@ -207,7 +241,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_dd_stats(const ImgDev* __
 }
 
 // y[off_i + z] = C_i[zigzag(z)] for z < k_i.
-template <int B>
+template <int B, int XF>
 __global__ __launch_bounds__(kGroupThreads) void k_gen_sense(const ImgDev* __restrict__ imgs,
                                                             const Tile* __restrict__ tiles, int ntiles,
                                                             const uint8_t* __restrict__ px,
@@ -217,7 +251,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_sense(const ImgDev* __res
   constexpr int P = B + 1;
   __shared__ GenShared<B> sh;
   if ((int)blockIdx.x >= ntiles) return;
-  gen_load_tables<B>(sh);
+  gen_load_tables<B, XF>(sh);
   __syncthreads();
   const Tile tl = tiles[blockIdx.x];
   const ImgDev im = imgs[tl.img];
@@ -245,7 +279,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_sense(const ImgDev* __res
 }
 
 // out = D^T C D per block, C zero beyond the block's k_i zigzag entries.
-template <int B>
+template <int B, int XF>
 __global__ __launch_bounds__(kGroupThreads) void k_gen_reconstruct(const ImgDev* __restrict__ imgs,
                                                                   const Tile* __restrict__ tiles, int ntiles,
                                                                   const float* __restrict__ y,
@@ -255,7 +289,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_reconstruct(const ImgDev*
   constexpr int P = B + 1;
   __shared__ GenShared<B> sh;
   if ((int)blockIdx.x >= ntiles) return;
-  gen_load_tables<B>(sh);
+  gen_load_tables<B, XF>(sh);
   __syncthreads();
   const Tile tl = tiles[blockIdx.x];
   const ImgDev im = imgs[tl.img];
@@ -287,7 +321,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_reconstruct(const ImgDev*
 // The transform half of an IDA iteration (as k_ida_step16): z^t = y - A x^t
 // + alpha z^{t-1} on the measured coefficients, v = x + A* z^t, and the
 // block's sum of (z^t)^2 in float64 (fixed butterfly order) in part[blk].
-template <int B>
+template <int B, int XF>
 __global__ __launch_bounds__(kGroupThreads) void k_gen_ida_step(const ImgDev* __restrict__ imgs,
                                                                const Tile* __restrict__ tiles, int ntiles,
                                                                const float* __restrict__ y,
@@ -299,7 +333,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_ida_step(const ImgDev* __
   constexpr int P = B + 1;
   __shared__ GenShared<B> sh;
   if ((int)blockIdx.x >= ntiles) return;
-  gen_load_tables<B>(sh);
+  gen_load_tables<B, XF>(sh);
   __syncthreads();
   const Tile tl = tiles[blockIdx.x];
   const ImgDev im = imgs[tl.img];

@@ -63,7 +63,7 @@ def test_descriptor_validation(native):
     assert _err({**base, "row_pitch": 258}) == native.ABCS_EINVAL      # pitch not multiple of 4
     assert _err({**base, "pixel_offset": 2}) == native.ABCS_EINVAL
     assert _err({**base, "method": 7}) == native.ABCS_EINVAL
-    assert _err({**base, "reserved": 1}) == native.ABCS_EINVAL
+    assert _err({**base, "transform": 2}) == native.ABCS_EINVAL
 
 
 def test_null_arguments(native):
