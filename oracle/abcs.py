@@ -17,6 +17,7 @@ of every floating-point sum is fixed:
   block_dct        C = D X D^T per block, fixed summation order
   block_idct       X = D^T C D per block
   bbv_stat         block boundary variation, eq 19 with edge rule
+  bbv_samples      the signed samples behind eq 19 (extra measurements)
   dd_stat          n_i = #{first m1 zigzag coefficients with |c| > T}
   apportion        capped largest-remainder split (eqs 22-23 with the cap
                    and redistribution rule stated after eq 22)
@@ -295,6 +296,50 @@ def bbv_stat(img, block, L, X0, nS):
             right = col_var(c0 + B, r0) if bx + 1 < nbx else col_var(c0 + B - 1, r0)
             out[by * nbx + bx] = top + left + bottom + right
     return out
+
+
+def bbv_sample_pairs(height, width, block, L, X0, nS):
+    """The pixel pairs (a, b) of every BBV sample (eq 19), as flat indices into
+    the cropped H' x W' image; the sample's value is I[a] - I[b] (a the later
+    pixel along the border).  Order: for each block in raster order its n_S
+    top-row then its n_S left-column samples; then the n_S bottom-row samples
+    of each block of the last block row; then the n_S right-column samples of
+    each block of the last block column (M_BBV pairs in all)."""
+    B = int(block)
+    Hc, Wc, nbx, nby, nB = geometry(height, width, B)
+    ks = [X0 + j * L for j in range(nS)]
+    a, b = [], []
+
+    def row(r, c0):
+        for k in ks:
+            a.append(r * Wc + c0 + k)
+            b.append(r * Wc + c0 + k - 1)
+
+    def col(c, r0):
+        for k in ks:
+            a.append((r0 + k) * Wc + c)
+            b.append((r0 + k - 1) * Wc + c)
+
+    for by in range(nby):
+        for bx in range(nbx):
+            row(by * B, bx * B)
+            col(bx * B, by * B)
+    for bx in range(nbx):
+        row((nby - 1) * B + B - 1, bx * B)
+    for by in range(nby):
+        col((nbx - 1) * B + B - 1, by * B)
+    return np.array(a, dtype=np.int64), np.array(b, dtype=np.int64)
+
+
+def bbv_samples(img, block, L, X0, nS):
+    """Signed BBV samples I[a] - I[b] in the order of bbv_sample_pairs; their
+    absolute values are the terms of eq 19, which the encoder measures anyway
+    and may send as extra measurements (Section V-A)."""
+    I = np.asarray(img).astype(np.int64)
+    Hc, Wc, _, _, _ = geometry(I.shape[0], I.shape[1], block)
+    flat = I[:Hc, :Wc].reshape(-1)
+    a, b = bbv_sample_pairs(I.shape[0], I.shape[1], block, L, X0, nS)
+    return flat[a] - flat[b]
 
 
 def dd_stat(img, block, m1, T, transform="dct"):

@@ -49,8 +49,31 @@ def identity_denoiser(v, sigma):
     return v
 
 
+def bbv_rows(bbv, height, width, block):
+    """(a, b, d) of the BBV difference rows: row (e_a - e_b) / sqrt 2 with
+    measurement d / sqrt 2, d the signed samples."""
+    d, L, X0, nS = bbv
+    a, b = abcs.bbv_sample_pairs(height, width, block, L, X0, nS)
+    return a, b, np.asarray(d, dtype=np.float64) / math.sqrt(2.0)
+
+
+def bbv_op(x, a, b):
+    """A_bbv x = (x[a] - x[b]) / sqrt 2 (x flattened)."""
+    xf = np.asarray(x, dtype=np.float64).reshape(-1)
+    return (xf[a] - xf[b]) / math.sqrt(2.0)
+
+
+def bbv_adjoint(z, a, b, shape):
+    """A_bbv* z: +z / sqrt 2 at pixel a, -z / sqrt 2 at pixel b of each row."""
+    out = np.zeros(int(np.prod(shape)), dtype=np.float64)
+    zs = np.asarray(z, dtype=np.float64) / math.sqrt(2.0)
+    np.add.at(out, a, zs)
+    np.add.at(out, b, -zs)
+    return out.reshape(shape)
+
+
 def ida(y, k, block, height, width, iters, damping, denoiser=identity_denoiser,
-        trace=None, transform="dct"):
+        trace=None, transform="dct", bbv=None):
     """Run `iters` IDA iterations for one image.
 
     y       measurements (float, packed as abcs.sense produces them)
@@ -58,23 +81,37 @@ def ida(y, k, block, height, width, iters, damping, denoiser=identity_denoiser,
     returns (x^T as a float64 (H', W') array, list of sigma^t)
     `trace`, if a list, receives (t, v^t, sigma^t) for every iteration.
     `transform` is the sensing transform of A ("dct" or "wht").
+    `bbv`, if given as (samples, L, X0, n_S), adds the BBV samples to A as
+    difference rows (e_a - e_b) / sqrt 2 (Section V-A: the phase-1 samples
+    may serve as additional reconstruction measurements): their residual
+    joins z, A* scatters it back to the two pixels, and m counts them.
     """
     Hc, Wc, nbx, nby, _ = abcs.geometry(height, width, block)
     y = np.asarray(y, dtype=np.float64)
-    m = y.size
+    if bbv is not None:
+        ba, bb, bd = bbv_rows(bbv, height, width, block)
+    else:
+        ba = bb = np.zeros(0, dtype=np.int64)
+        bd = np.zeros(0)
+    m = y.size + bd.size
     alpha = 1.0 / float(damping)
     x = np.zeros((Hc, Wc), dtype=np.float64)
-    z_prev = np.zeros(m, dtype=np.float64)
+    z_prev = np.zeros(y.size, dtype=np.float64)
+    zb_prev = np.zeros(bd.size, dtype=np.float64)
     sigmas = []
     for t in range(int(iters)):
         r = y - abcs.sense_op(x, block, k, transform)
         z = r + alpha * z_prev
-        sigma = math.sqrt(float(np.sum(z * z)) / m) if m else 0.0
+        zb = (bd - bbv_op(x, ba, bb)) + alpha * zb_prev
+        sigma = math.sqrt((float(np.sum(z * z)) + float(np.sum(zb * zb))) / m) if m else 0.0
         v = x + abcs.sense_adjoint(z, block, k, nby, nbx, transform)
+        if bd.size:
+            v = v + bbv_adjoint(zb, ba, bb, v.shape)
         if trace is not None:
             trace.append((t, v.copy(), sigma))
         x = np.asarray(denoiser(v, sigma), dtype=np.float64)
         z_prev = z
+        zb_prev = zb
         sigmas.append(sigma)
     return x, sigmas
 

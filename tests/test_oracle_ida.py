@@ -109,3 +109,69 @@ def test_damp_d_infinite_damping_is_ida_without_memory(case):
     xa, sa, _ = ida.amp(y, k, 16, 64, 48, 5, math.inf, b, denoiser=lambda v, s: 0.9 * v, algorithm="damp-d")
     xi, si = ida.ida(y, k, 16, 64, 48, 5, math.inf, denoiser=lambda v, s: 0.9 * v)
     assert np.allclose(xa, xi, rtol=0, atol=1e-9) and np.allclose(sa, si, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# BBV samples as extra difference rows of A (Section V-A)
+# ---------------------------------------------------------------------------
+
+def _bbv_case(seed=21, H=64, W=80, cr=0.2):
+    img = synth.synth_image(seed, H, W)
+    s = abcs.budget_scalars(H, W, 16, cr, abcs.BBV)
+    return img, s
+
+
+def test_bbv_samples_rebuild_the_statistic():
+    img, s = _bbv_case()
+    L, X0, nS = s["L"], s["X0"], s["nS"]
+    d = abcs.bbv_samples(img, 16, L, X0, nS)
+    nbx, nby, nB = 5, 4, 20
+    assert d.size == 2 * nS * nB + nS * (nbx + nby)
+    a, b = abcs.bbv_sample_pairs(64, 80, 16, L, X0, nS)
+    assert np.all((a - b == 1) | (a - b == 80))
+    # BBV_i = own top + own left + top of the block below (own bottom edge in
+    # the last row) + left of the block to the right (own right edge)
+    ad = np.abs(d)
+    top = ad[:2 * nS * nB].reshape(nB, 2, nS)[:, 0].sum(axis=1).reshape(nby, nbx)
+    left = ad[:2 * nS * nB].reshape(nB, 2, nS)[:, 1].sum(axis=1).reshape(nby, nbx)
+    bottom_edge = ad[2 * nS * nB:2 * nS * nB + nS * nbx].reshape(nbx, nS).sum(axis=1)
+    right_edge = ad[2 * nS * nB + nS * nbx:].reshape(nby, nS).sum(axis=1)
+    below = np.vstack([top[1:], bottom_edge[None, :]])
+    right = np.hstack([left[:, 1:], right_edge[:, None]])
+    want = (top + left + below + right).reshape(-1)
+    assert np.array_equal(want, abcs.bbv_stat(img, 16, L, X0, nS))
+
+
+def test_bbv_rows_operator_and_adjoint():
+    img, s = _bbv_case()
+    d = abcs.bbv_samples(img, 16, s["L"], s["X0"], s["nS"])
+    a, b, dm = ida.bbv_rows((d, s["L"], s["X0"], s["nS"]), 64, 80, 16)
+    # the rows measure the image exactly
+    assert np.allclose(ida.bbv_op(img.astype(np.float64), a, b), dm, rtol=0, atol=1e-12)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((64, 80))
+    z = rng.standard_normal(d.size)
+    assert float(np.dot(ida.bbv_op(x, a, b), z)) == pytest.approx(float(np.sum(x * ida.bbv_adjoint(z, a, b, x.shape))), rel=1e-12)
+
+
+def test_ida_with_bbv_rows_first_iterate_and_sigma():
+    """x0 = 0: z0 = [y; d / sqrt 2], sigma0 = sqrt((|y|^2 + |d|^2 / 2) / (m + M_BBV)),
+    and with the identity denoiser x1 = I_o plus d / 2 added at the later and
+    subtracted at the earlier pixel of every sample."""
+    img, s = _bbv_case()
+    k, _ = abcs.budget(img, 16, 0.2, abcs.BBV)
+    y = abcs.sense(img, 16, k)
+    d = abcs.bbv_samples(img, 16, s["L"], s["X0"], s["nS"])
+    x1, sig = ida.ida(y, k, 16, 64, 80, 1, 2.0, bbv=(d, s["L"], s["X0"], s["nS"]))
+    want_sigma = math.sqrt((float(np.sum(y * y)) + float(np.sum(d.astype(np.float64) ** 2)) / 2) / (y.size + d.size))
+    assert sig[0] == pytest.approx(want_sigma, rel=1e-12)
+    want = abcs.reconstruct(y, 16, k, 64, 80).reshape(-1)
+    a, b = abcs.bbv_sample_pairs(64, 80, 16, s["L"], s["X0"], s["nS"])
+    for ai, bi, di in zip(a, b, d):
+        want[ai] += di / 2.0
+        want[bi] -= di / 2.0
+    assert np.max(np.abs(x1.reshape(-1) - want)) < 1e-9
+    # without samples the loop is unchanged
+    x_plain, _ = ida.ida(y, k, 16, 64, 80, 3, 2.0)
+    x_none, _ = ida.ida(y, k, 16, 64, 80, 3, 2.0, bbv=None)
+    assert np.array_equal(x_plain, x_none)
