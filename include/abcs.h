@@ -117,6 +117,9 @@ typedef struct abcs_image {
                             ZZ: n_B floor(B^2 C_R); BBV: M - M_BBV; DD: M    */
   int32_t cropped_height;/* H'                                               */
   int32_t cropped_width; /* W'                                               */
+  int64_t bbv_offset;    /* first BBV sample of this image (abcs_bbv_samples) */
+  int64_t n_bbv;         /* BBV samples: 2 n_S n_B + n_S (n_bx + n_by) for an
+                            adaptive BBV image, else 0                       */
 } abcs_image;
 
 typedef struct abcs_plan abcs_plan; /* opaque */
@@ -212,6 +215,28 @@ int ida_iterate(const abcs_plan* plan, const float* d_y, const int32_t* d_k, con
 int ida_refine(const abcs_plan* plan, const float* d_y, const int32_t* d_k, const int64_t* d_offsets,
                int iters, double damping, int denoiser, const void* d_params, float* d_x,
                float* d_sigma_trace, void* d_ws, size_t ws_bytes, void* stream);
+
+/* The signed BBV samples (Section V-A: the encoder measures them for eq 19
+ * and may send them as extra reconstruction measurements): each is
+ * d = I[a] - I[b] for two adjacent pixels on a block border, a the later one
+ * along the border.  Per BBV image, at its bbv_offset: for each block in
+ * raster order its n_S top-row then n_S left-column samples; then the n_S
+ * bottom-row samples of each block of the last block row; then the n_S
+ * right-column samples of each block of the last block column.
+ * d_samples: out, float[sum of n_bbv] (exact integers).  Errors as
+ * abcs_budget. */
+int abcs_bbv_samples(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, float* d_samples,
+                     void* stream);
+
+/* ida_refine with the BBV samples as extra rows of A: every sample adds the
+ * row (e_a - e_b) / sqrt 2 with measurement d / sqrt 2, so its residual joins
+ * z^t (eqs 25, 28), A* adds it back to the two pixels (eq 13) and m of eq 15
+ * counts the samples.  Images that are not adaptive BBV images run as in
+ * ida_refine.  d_bbv: float[sum of n_bbv] as written by abcs_bbv_samples.
+ * Other arguments, workspace and errors as ida_refine. */
+int ida_refine_bbv(const abcs_plan* plan, const float* d_y, const int32_t* d_k, const int64_t* d_offsets,
+                   const float* d_bbv, int iters, double damping, int denoiser, const void* d_params, float* d_x,
+                   float* d_sigma_trace, void* d_ws, size_t ws_bytes, void* stream);
 
 /* D-AMP and DAMP-D (eqs 13-15 with the Onsager coefficient of eq 24, or its
  * damped form eq 27), the algorithms IDA is derived from.  Same loop as

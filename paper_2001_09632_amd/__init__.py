@@ -11,4 +11,5 @@ from .api import (ZZ, BBV, DD, Plan, AbcsError, budget, sense, reconstruct,  # n
                   denoise, denoise_workspace_bytes, cnn_param_count, cnn_train_step,
                   cnn_train_workspace_bytes, IdaGraph, PRECISIONS,
                   amp_refine, amp_workspace_bytes, ALGORITHMS, threshold,
-                  threshold_workspace_bytes, budget_correlation, RULES, TRANSFORMS)
+                  threshold_workspace_bytes, budget_correlation, RULES, TRANSFORMS,
+                  bbv_samples, ida_refine_bbv)

@@ -15,6 +15,7 @@ EXPORTS = [
     "abcs_cnn_param_count", "abcs_cnn_train_workspace_bytes", "abcs_cnn_train_step",
     "ida_graph_create", "ida_graph_launch", "ida_graph_destroy", "amp_workspace_bytes", "amp_refine",
     "abcs_threshold_workspace_bytes", "abcs_threshold", "abcs_budget_correlation",
+    "abcs_bbv_samples", "ida_refine_bbv",
 ]
 
 
@@ -32,6 +33,7 @@ class ImageDesc(ctypes.Structure):
         ("block_offset", ctypes.c_int64), ("meas_offset", ctypes.c_int64),
         ("out_offset", ctypes.c_int64), ("n_meas", ctypes.c_int64),
         ("cropped_height", ctypes.c_int32), ("cropped_width", ctypes.c_int32),
+        ("bbv_offset", ctypes.c_int64), ("n_bbv", ctypes.c_int64),
     ]
 
 
@@ -85,6 +87,8 @@ def lib():
     L.abcs_threshold_workspace_bytes.restype = sz
     L.abcs_threshold.argtypes = [vp, vp, i64, i32, vp, vp, vp, sz, vp]
     L.abcs_budget_correlation.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.abcs_bbv_samples.argtypes = [vp, vp, i64, vp, vp]
+    L.ida_refine_bbv.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp, sz, vp]
     L.ida_graph_destroy.argtypes = [vp]
     L.ida_graph_destroy.restype = None
     for name in EXPORTS:

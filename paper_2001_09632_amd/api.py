@@ -60,6 +60,7 @@ class Plan:
             out = ImageDesc()
             check(lib().abcs_plan_image(self._h, i, ctypes.byref(out)))
             self.images.append({f: getattr(out, f) for f, _ in ImageDesc._fields_})
+        self.bbv_total = sum(d["n_bbv"] for d in self.images)
 
     @property
     def handle(self):
@@ -122,6 +123,23 @@ def ida_refine(plan, y, k, offsets, x, iters, damping=2.0, denoiser="identity", 
     check(lib().ida_refine(plan.handle, _ptr(y), _ptr(k), _ptr(offsets), int(iters), float(damping), d,
                            _ptr(params), _ptr(x), _ptr(sigma_trace), _ptr(workspace), ws_bytes,
                            _stream(stream)))
+
+
+def bbv_samples(plan, px, out, stream=None):
+    """abcs_bbv_samples: out float32[plan.bbv_total] <- the signed BBV samples."""
+    check(lib().abcs_bbv_samples(plan.handle, _ptr(px), px.numel() * px.element_size(), _ptr(out),
+                                 _stream(stream)))
+
+
+def ida_refine_bbv(plan, y, k, offsets, bbv, x, iters, damping=2.0, denoiser="identity", params=None,
+                   sigma_trace=None, workspace=None, stream=None):
+    """ida_refine_bbv: ida_refine with the BBV samples (float32[plan.bbv_total])
+    as extra difference rows of A."""
+    d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().ida_refine_bbv(plan.handle, _ptr(y), _ptr(k), _ptr(offsets), _ptr(bbv), int(iters), float(damping),
+                               d, _ptr(params), _ptr(x), _ptr(sigma_trace), _ptr(workspace), ws_bytes,
+                               _stream(stream)))
 
 
 ALGORITHMS = {"damp": 1, "damp-d": 2}

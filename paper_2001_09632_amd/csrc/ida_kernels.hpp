@@ -93,18 +93,24 @@ __global__ __launch_bounds__(kGroupThreads) void k_ida_step16(const ImgDev* __re
 
 // sigma_i = sqrt(sum of the image's block partials / m_i), one workgroup per
 // image; partials are added in block order by a fixed tree.  Also appends
-// sigma to trace[t * n + i] when trace is not null.
+// sigma to trace[t * n + i] when trace is not null.  With part_bbv, the BBV
+// images' sample residuals (per-block partials) and sample count join the sum
+// and m.
 __global__ __launch_bounds__(kGroupThreads) void k_ida_sigma(const ImgDev* __restrict__ imgs,
                                                             const double* __restrict__ part,
                                                             float* __restrict__ sigma, float* __restrict__ trace,
-                                                            int n_imgs, int t) {
+                                                            int n_imgs, int t,
+                                                            const double* __restrict__ part_bbv) {
   __shared__ double sh[kGroupThreads];
   const ImgDev im = imgs[blockIdx.x];
   const int tid = threadIdx.x;
   const int per = (im.nB + kGroupThreads - 1) / kGroupThreads;
   const int i0 = min(im.nB, tid * per), i1 = min(im.nB, i0 + per);
+  // BBV images with sample rows: their residuals and their count join m
+  const bool rows = part_bbv != nullptr && im.mode == kModeBBV;
+  const int64_t m = im.n_meas + (rows ? 2LL * im.nS * im.nB + (int64_t)im.nS * (im.nbx + im.nby) : 0);
   double s = 0.0;
-  for (int i = i0; i < i1; ++i) s += part[im.blk_off + i];
+  for (int i = i0; i < i1; ++i) s += part[im.blk_off + i] + (rows ? part_bbv[im.blk_off + i] : 0.0);
   sh[tid] = s;
   __syncthreads();
   for (int w = kGroupThreads / 2; w > 0; w >>= 1) {
@@ -112,9 +118,136 @@ __global__ __launch_bounds__(kGroupThreads) void k_ida_sigma(const ImgDev* __res
     __syncthreads();
   }
   if (tid == 0) {
-    const float sg = im.n_meas > 0 ? (float)sqrt(sh[0] / (double)im.n_meas) : 0.f;
+    const float sg = m > 0 ? (float)sqrt(sh[0] / (double)m) : 0.f;
     sigma[blockIdx.x] = sg;
     if (trace) trace[(int64_t)t * n_imgs + blockIdx.x] = sg;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BBV samples as extra measurements (Section V-A): every sample of eq 19 is a
+// signed difference d = I[a] - I[b] of two adjacent pixels.  Layout per BBV
+// image (at its sample offset): for each block in raster order its n_S
+// top-row then its n_S left-column samples; then the n_S bottom-row samples
+// of each block of the last block row; then the n_S right-column samples of
+// each block of the last block column.  In IDA they are rows (e_a - e_b)/sqrt 2
+// of A with measurements d/sqrt 2; every sample's two pixels lie in its own
+// block, so one thread per block owns them.
+// ---------------------------------------------------------------------------
+
+struct BbvSample {
+  int r, c;      // pixel a (row, column in the cropped image)
+  int dr, dc;    // b = a - (dr, dc)
+  int64_t slot;  // position in the image's sample list
+};
+
+// The s-th sample (0 <= s < bbv_block_count) of block (by, bx).
+__device__ __forceinline__ int bbv_block_count(const ImgDev& im, int by, int bx) {
+  return 2 * im.nS + (by + 1 == im.nby ? im.nS : 0) + (bx + 1 == im.nbx ? im.nS : 0);
+}
+
+__device__ __forceinline__ BbvSample bbv_block_sample(const ImgDev& im, int by, int bx, int s) {
+  const int B = im.B, nS = im.nS, r0 = by * B, c0 = bx * B;
+  const int64_t nB = im.nB, blk = (int64_t)by * im.nbx + bx;
+  int part = s / nS;
+  const int j = s - part * nS, k = im.X0 + j * im.L;
+  if (part == 2 && by + 1 != im.nby) part = 3;  // no bottom edge: the next group is the right edge
+  BbvSample q;
+  switch (part) {
+    case 0:  // top row
+      q = BbvSample{r0, c0 + k, 0, 1, blk * 2 * nS + j};
+      break;
+    case 1:  // left column
+      q = BbvSample{r0 + k, c0, 1, 0, blk * 2 * nS + nS + j};
+      break;
+    case 2:  // bottom edge of the last block row
+      q = BbvSample{r0 + B - 1, c0 + k, 0, 1, 2 * nS * nB + (int64_t)bx * nS + j};
+      break;
+    default:  // right edge of the last block column
+      q = BbvSample{r0 + k, c0 + B - 1, 1, 0, 2 * nS * nB + (int64_t)nS * im.nbx + (int64_t)by * nS + j};
+      break;
+  }
+  return q;
+}
+
+// Signed samples of every block of the BBV tiles (one thread per block).
+__global__ __launch_bounds__(kGroupThreads) void k_bbv_samples(const ImgDev* __restrict__ imgs,
+                                                              const Tile* __restrict__ tiles, int ntiles,
+                                                              const uint8_t* __restrict__ px,
+                                                              const int64_t* __restrict__ bbv_off,
+                                                              float* __restrict__ out) {
+  const int t = blockIdx.x * kGroupThreads + threadIdx.x;
+  const int ti = t / kTileBlocks, b = t % kTileBlocks;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  if (b >= tl.count) return;
+  const ImgDev im = imgs[tl.img];
+  const int by = tl.by, bx = tl.first - tl.by * im.nbx + b;
+  const uint8_t* base = px + im.px_off;
+  float* o = out + bbv_off[tl.img];
+  const int n = bbv_block_count(im, by, bx);
+  for (int s = 0; s < n; ++s) {
+    const BbvSample q = bbv_block_sample(im, by, bx, s);
+    const int a = base[(int64_t)q.r * im.pitch + q.c];
+    const int bv = base[(int64_t)(q.r - q.dr) * im.pitch + (q.c - q.dc)];
+    o[q.slot] = (float)(a - bv);
+  }
+}
+
+// Before the transform step: zb = (d - (x_a - x_b)) / sqrt 2 + alpha zb_prev
+// (x = 0 and zb_prev = 0 at t = 0); pb[blk] = sum of zb^2 in sample order.
+__global__ __launch_bounds__(kGroupThreads) void k_ida_bbv_residual(const ImgDev* __restrict__ imgs,
+                                                                   const Tile* __restrict__ tiles, int ntiles,
+                                                                   const float* __restrict__ d,
+                                                                   const int64_t* __restrict__ bbv_off,
+                                                                   const float* __restrict__ x,
+                                                                   float* __restrict__ zb, double* __restrict__ pb,
+                                                                   float alpha, int first) {
+  const int t = blockIdx.x * kGroupThreads + threadIdx.x;
+  const int ti = t / kTileBlocks, b = t % kTileBlocks;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  if (b >= tl.count) return;
+  const ImgDev im = imgs[tl.img];
+  const int by = tl.by, bx = tl.first - tl.by * im.nbx + b;
+  const int64_t off = bbv_off[tl.img];
+  const float* xi = x + im.out_off;
+  const float r2 = 0.70710678118654752f;  // 1 / sqrt 2
+  double acc = 0.0;
+  const int n = bbv_block_count(im, by, bx);
+  for (int s = 0; s < n; ++s) {
+    const BbvSample q = bbv_block_sample(im, by, bx, s);
+    float ax = 0.f;
+    if (!first) ax = (xi[(int64_t)q.r * im.Wc + q.c] - xi[(int64_t)(q.r - q.dr) * im.Wc + (q.c - q.dc)]) * r2;
+    const float zo = first ? 0.f : zb[off + q.slot];
+    const float zn = (d[off + q.slot] * r2 - ax) + alpha * zo;
+    zb[off + q.slot] = zn;
+    acc += (double)zn * (double)zn;
+  }
+  pb[im.blk_off + tl.first + b] = acc;
+}
+
+// After the transform step: v += A_bbv* zb (each block's samples in order).
+__global__ __launch_bounds__(kGroupThreads) void k_ida_bbv_scatter(const ImgDev* __restrict__ imgs,
+                                                                  const Tile* __restrict__ tiles, int ntiles,
+                                                                  const int64_t* __restrict__ bbv_off,
+                                                                  const float* __restrict__ zb, float* v) {
+  const int t = blockIdx.x * kGroupThreads + threadIdx.x;
+  const int ti = t / kTileBlocks, b = t % kTileBlocks;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  if (b >= tl.count) return;
+  const ImgDev im = imgs[tl.img];
+  const int by = tl.by, bx = tl.first - tl.by * im.nbx + b;
+  const int64_t off = bbv_off[tl.img];
+  float* vi = v + im.out_off;
+  const float r2 = 0.70710678118654752f;
+  const int n = bbv_block_count(im, by, bx);
+  for (int s = 0; s < n; ++s) {
+    const BbvSample q = bbv_block_sample(im, by, bx, s);
+    const float h = zb[off + q.slot] * r2;
+    vi[(int64_t)q.r * im.Wc + q.c] += h;
+    vi[(int64_t)(q.r - q.dr) * im.Wc + (q.c - q.dc)] -= h;
   }
 }
 
