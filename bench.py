@@ -209,6 +209,31 @@ def ida_section(dev, weights_path):
         g.ida_refine(plan, y, k, off, xa, it, df, "cnn", params=prm, workspace=wsi)
         sweep[str(df)] = round(scores(xa)[0], 3)
     rec["ida_psnr_by_damping"] = sweep
+
+    # The BBV images' phase-1 samples as extra measurements (Section V-A):
+    # learned IDA on the BBV images with and without them as rows of A.
+    px = torch.from_numpy(np.concatenate([im.reshape(-1) for im in imgs])).to(dev)
+    bbv = torch.empty(max(1, plan.bbv_total), dtype=torch.float32, device=dev)
+    g.bbv_samples(plan, px, bbv)
+    sel = [i for i in range(n) if methods[i] == "bbv"]
+
+    def psnr_sel(x):
+        h = x.cpu().numpy()
+        out = []
+        for i in sel:
+            d = plan.images[i]
+            out.append(quality.psnr(h[d["out_offset"]:d["out_offset"] + imgs[i].size].reshape(imgs[i].shape), imgs[i]))
+        return round(float(np.mean(out)), 3)
+
+    g.ida_refine(plan, y, k, off, xa, it, 2.0, "cnn", params=prm, workspace=wsi)
+    p_plain = psnr_sel(xa)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.ida_refine_bbv(plan, y, k, off, bbv, xa, it, 2.0, "cnn", params=prm, workspace=wsi)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rec["bbv_rows"] = {"images": len(sel), "iters": it, "samples": int(plan.bbv_total),
+                       "psnr_without": p_plain, "psnr_with": psnr_sel(xa), "ms_per_batch": round(dt * 1e3, 2)}
     return rec
 
 
@@ -341,7 +366,7 @@ def bounds_section(dev, plan, px, k, out, images):
     ref = torch.from_numpy(images).to(dev).float()
 
     def psnr(buf):
-        x = buf.view(len(METHODS), len(SUBRATES), n_img, H, W)
+        x = buf.view(len(METHODS), len(SUBRATES), n_img, H, W).clamp(0, 255)
         mse = ((x - ref[None, None]) ** 2).mean(dim=(3, 4))
         return (10.0 * torch.log10(255.0 ** 2 / mse)).mean(dim=2)  # (method, C_R)
 
@@ -370,6 +395,46 @@ def bounds_section(dev, plan, px, k, out, images):
     res["p_value_max_by_cr"] = {meth: {str(cr): float("%.3g" % v) for cr, v in zip(SUBRATES, pmax[i])}
                                 for i, meth in enumerate(METHODS)}
     return res
+
+
+def wht_section(dev, px, images, out_dct):
+    """Walsh-Hadamard sensing (Section IV's alternative transform) on the same
+    640 encodings: time per budget + sense + decode step (vector-ALU kernels)
+    and mean PSNR per C_R next to the DCT's."""
+    import torch
+    import paper_2001_09632_amd as g
+    n_img = len(SEEDS)
+    plan = g.Plan([dict(e, transform="wht") for e in entries()])
+    k = torch.empty(plan.blocks, dtype=torch.int32, device=dev)
+    off = torch.empty(plan.blocks, dtype=torch.int64, device=dev)
+    stat = torch.empty(plan.blocks, dtype=torch.int32, device=dev)
+    y = torch.empty(plan.meas, dtype=torch.float32, device=dev)
+    out = torch.empty(plan.pixels, dtype=torch.float32, device=dev)
+    ref = torch.from_numpy(images).to(dev).float()
+
+    def step():
+        g.budget(plan, px, k, off, stat)
+        g.sense(plan, px, k, off, y)
+        g.reconstruct(plan, y, k, off, out)
+
+    def psnr(buf):
+        x = buf.view(len(METHODS), len(SUBRATES), n_img, H, W).clamp(0, 255)
+        mse = ((x - ref[None, None]) ** 2).mean(dim=(3, 4))
+        return (10.0 * torch.log10(255.0 ** 2 / mse)).mean(dim=2)
+
+    step()
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record()
+    for _ in range(3):
+        step()
+    e[1].record()
+    torch.cuda.synchronize()
+    ms = e[0].elapsed_time(e[1]) / 3
+    pw, pd = psnr(out).tolist(), psnr(out_dct).tolist()
+    return {"ms_per_step": round(ms, 3), "mpix_s": round(plan.pixels / (ms * 1e-3) / 1e6, 1),
+            "psnr_db_by_cr": {f"{xf}-{m}": {str(cr): round(v, 3) for cr, v in zip(SUBRATES, tab[i])}
+                              for xf, tab in (("wht", pw), ("dct", pd)) for i, m in enumerate(METHODS)}}
 
 
 def cpu_baseline(images, n_images, deadline_s=30.0):
@@ -404,6 +469,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ida", action="store_true")
     ap.add_argument("--no-bounds", action="store_true", help="skip the THI / THB bounds section")
+    ap.add_argument("--no-wht", action="store_true", help="skip the Walsh-Hadamard section")
     ap.add_argument("--cnn-weights", default=os.path.join(ROOT, "paper_2001_09632_amd", "weights", "ida_cnn.npy"))
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a device-to-device copy of this many MiB (5 times) and exit; "
@@ -510,6 +576,11 @@ def main():
         log("bounds")
         bounds = bounds_section(dev, plan, px, k, out32, images)
 
+    wht = None
+    if not args.no_wht:
+        log("wht")
+        wht = wht_section(dev, px, images, out32)
+
     ida = None
     if not args.no_ida:
         log("ida")
@@ -547,6 +618,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "bounds": bounds,
+        "wht": wht,
         "ida": ida,
         "stream": stream,
     }
