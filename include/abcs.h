@@ -66,7 +66,10 @@ typedef enum abcs_status {
 typedef enum abcs_denoiser {
   ABCS_DENOISE_IDENTITY = 0, /* D(v) = v: the loop without a denoiser        */
   ABCS_DENOISE_BM3D = 1,     /* plain BM3D (Dabov et al., ref [22])          */
-  ABCS_DENOISE_CNN = 2       /* learned 8-layer 3x3 CNN (parameters passed)  */
+  ABCS_DENOISE_CNN = 2,      /* learned 8-layer 3x3 CNN (parameters passed)  */
+  ABCS_DENOISE_DNCNN = 3     /* DnCNN-17 with batch normalisation (Section
+                                VI-4); parameters: the blob followed by the
+                                running statistics (abcs_dncnn_*_count)     */
 } abcs_denoiser;
 
 /* Sensing transform of an image (Section IV): the 2-D DCT-II, or the 2-D
@@ -363,6 +366,33 @@ int abcs_threshold(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes,
  * Errors: EINVAL (null or misaligned buffer), EHIP. */
 int abcs_budget_correlation(const abcs_plan* plan, const int32_t* d_m, const int32_t* d_m_hat, double* d_rho,
                             double* d_p, void* stream);
+
+/* DnCNN-17 (Section VI-4): layer 1 3x3 conv 2 -> 64 + bias + ReLU; layers
+ * 2..16 3x3 conv 64 -> 64 (no bias) + batch normalisation (gamma, beta) +
+ * ReLU; layer 17 3x3 conv 64 -> 1 + bias; the same input [v/255, sigma map]
+ * and residual output v - 255 f as the 8-layer network, bfloat16 weights and
+ * activations, float32 sums.  The parameter blob holds W1 [64][3][3][2], b1
+ * [64], then per middle layer W [64][3][3][64], gamma [64], beta [64], then
+ * W17 [1][3][3][64], b17 (abcs_dncnn_param_count floats).  The running
+ * statistics hold per middle layer mean [64] then variance [64]
+ * (abcs_dncnn_running_count floats).  As a denoiser (ABCS_DENOISE_DNCNN) the
+ * parameter pointer addresses the blob immediately followed by the running
+ * statistics; normalisation is folded into the convolutions (inference). */
+size_t abcs_dncnn_param_count(void);
+size_t abcs_dncnn_running_count(void);
+
+/* One DnCNN training step: forward with batch statistics (mean and biased
+ * variance over all pixels of the batch, eps 1e-5, sums in float64), MSE loss
+ * as abcs_cnn_train_step, gradients of every parameter (d_grad, nullable,
+ * float[param_count]), and, when lr > 0, Adam as abcs_cnn_train_step.
+ * d_running (nullable): the running statistics, moved by 0.1 towards the
+ * batch statistics.  d_ws: abcs_dncnn_train_workspace_bytes(plan) bytes.
+ * Errors as abcs_cnn_train_step. */
+size_t abcs_dncnn_train_workspace_bytes(const abcs_plan* plan);
+int abcs_dncnn_train_step(const abcs_plan* plan, float* d_params, float* d_adam_m, float* d_adam_v,
+                          float* d_running, int64_t step, float lr, const float* d_input, const float* d_sigma,
+                          const float* d_target, float* d_loss, float* d_grad, void* d_ws, size_t ws_bytes,
+                          void* stream);
 
 /* Host copy of the float64 orthonormal DCT-II basis the library uses,
  * D[u*B + j] = s_u cos((2j+1) u pi / (2B)), for checking.  B in {8, 16, 32}. */

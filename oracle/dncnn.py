@@ -26,8 +26,9 @@ beta [64]; then W17 [1][3][3][64], b17 [1].  Running statistics: for each
 middle layer mean [64] then variance [64].
 
 `round_act`, when given, is applied to every stored activation and to the
-pre-normalisation values (the GPU keeps them in bfloat16); by default every
-value is float64.
+pre-normalisation values, and `round_grad` to the gradients passed between
+layers (the GPU keeps all of these in bfloat16); by default every value is
+float64.
 
 Parity: pinned by tests/test_oracle_dncnn.py: central finite differences of
 the loss (weights, gamma, beta), the normalised values' zero mean and unit
@@ -137,9 +138,13 @@ def forward(blob, v, sigma, running=None, train=True, keep=False, round_act=None
     return (out, cache) if keep else out
 
 
-def loss_and_grad(blob, v, sigma, target, round_act=None):
+def loss_and_grad(blob, v, sigma, target, round_act=None, round_grad=None):
     """Training mode: MSE of D(v)/255 against target/255, its gradient blob,
-    and the batch statistics [(mean, var)] of the 15 normalisations."""
+    and the batch statistics [(mean, var)] of the 15 normalisations.
+    `round_grad`, when given, is applied to the gradients passed between
+    layers (at each normalisation's output and input), where the GPU stores
+    them in bfloat16."""
+    rg = round_grad or _ident
     w1, b1, mids, w17, b17 = unpack(blob)
     out, c = forward(blob, v, sigma, train=True, keep=True, round_act=round_act)
     n = out.size
@@ -151,18 +156,19 @@ def loss_and_grad(blob, v, sigma, target, round_act=None):
     gmids = [None] * N_MID
     for l in range(N_MID - 1, -1, -1):
         w, gam, _ = mids[l]
-        gy = ga * (c["a"][l + 1] > 0.0)                  # through the ReLU
+        gy = rg(ga * (c["a"][l + 1] > 0.0))              # through the ReLU
         zhat = c["zhat"][l]
         _, var = c["stats"][l]
         cnt = gy.shape[0] * gy.shape[1] * gy.shape[2]
         ggam = (gy * zhat).sum(axis=(0, 1, 2))
         gbet = gy.sum(axis=(0, 1, 2))
         gzh = gy * gam
-        gz = (gzh - gzh.sum(axis=(0, 1, 2)) / cnt - zhat * (gzh * zhat).sum(axis=(0, 1, 2)) / cnt) / np.sqrt(var + BN_EPS)
+        gz = rg((gzh - gzh.sum(axis=(0, 1, 2)) / cnt - zhat * (gzh * zhat).sum(axis=(0, 1, 2)) / cnt)
+                / np.sqrt(var + BN_EPS))
         gw, _ = ocnn.conv3x3_weight_grad(c["a"][l], gz)
         gmids[l] = (gw, ggam, gbet)
         ga = ocnn.conv3x3_input_grad(gz, w)               # dL/da_l
-    g1 = ga * (c["a"][0] > 0.0)
+    g1 = rg(ga * (c["a"][0] > 0.0))
     gw1, gb1 = ocnn.conv3x3_weight_grad(c["x0"], g1)
     return loss, pack(gw1, gb1, gmids, gw17, gb17), c["stats"]
 

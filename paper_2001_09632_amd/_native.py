@@ -16,6 +16,8 @@ EXPORTS = [
     "ida_graph_create", "ida_graph_launch", "ida_graph_destroy", "amp_workspace_bytes", "amp_refine",
     "abcs_threshold_workspace_bytes", "abcs_threshold", "abcs_budget_correlation",
     "abcs_bbv_samples", "ida_refine_bbv",
+    "abcs_dncnn_param_count", "abcs_dncnn_running_count", "abcs_dncnn_train_workspace_bytes",
+    "abcs_dncnn_train_step",
 ]
 
 
@@ -89,12 +91,20 @@ def lib():
     L.abcs_budget_correlation.argtypes = [vp, vp, vp, vp, vp, vp]
     L.abcs_bbv_samples.argtypes = [vp, vp, i64, vp, vp]
     L.ida_refine_bbv.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp, sz, vp]
+    L.abcs_dncnn_param_count.argtypes = []
+    L.abcs_dncnn_param_count.restype = sz
+    L.abcs_dncnn_running_count.argtypes = []
+    L.abcs_dncnn_running_count.restype = sz
+    L.abcs_dncnn_train_workspace_bytes.argtypes = [vp]
+    L.abcs_dncnn_train_workspace_bytes.restype = sz
+    L.abcs_dncnn_train_step.argtypes = [vp, vp, vp, vp, vp, i64, ctypes.c_float, vp, vp, vp, vp, vp, vp, sz, vp]
     L.ida_graph_destroy.argtypes = [vp]
     L.ida_graph_destroy.restype = None
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("abcs_plan_destroy", "abcs_last_error", "ida_workspace_bytes", "ida_graph_destroy",
                         "amp_workspace_bytes", "abcs_threshold_workspace_bytes",
+                        "abcs_dncnn_param_count", "abcs_dncnn_running_count", "abcs_dncnn_train_workspace_bytes",
                         "abcs_denoise_workspace_bytes", "abcs_cnn_param_count",
                         "abcs_cnn_train_workspace_bytes"):
             f.restype = ctypes.c_int

@@ -105,8 +105,8 @@ def reconstruct(plan, y, k, offsets, out, stream=None, precision="fp32"):
                                  _prec(precision), _stream(stream)))
 
 
-IDENTITY, BM3D, CNN = 0, 1, 2
-DENOISERS = {"identity": IDENTITY, "bm3d": BM3D, "cnn": CNN}
+IDENTITY, BM3D, CNN, DNCNN = 0, 1, 2, 3
+DENOISERS = {"identity": IDENTITY, "bm3d": BM3D, "cnn": CNN, "dncnn": DNCNN}
 
 
 def ida_workspace_bytes(plan, denoiser):
@@ -258,6 +258,28 @@ def budget_correlation(plan, m, m_hat, rho, p=None, stream=None):
     """abcs_budget_correlation: rho float64[n] <- Pearson(m, m_hat) per image,
     p float64[n] (or None) <- two-sided p-value of rho = 0."""
     check(lib().abcs_budget_correlation(plan.handle, _ptr(m), _ptr(m_hat), _ptr(rho), _ptr(p), _stream(stream)))
+
+
+def dncnn_param_count():
+    return int(lib().abcs_dncnn_param_count())
+
+
+def dncnn_running_count():
+    return int(lib().abcs_dncnn_running_count())
+
+
+def dncnn_train_workspace_bytes(plan):
+    return int(lib().abcs_dncnn_train_workspace_bytes(plan.handle))
+
+
+def dncnn_train_step(plan, params, adam_m, adam_v, running, step, lr, x_in, sigma, target, loss, grad=None,
+                     workspace=None, stream=None):
+    """abcs_dncnn_train_step on device tensors (float32); running (or None)
+    float32[running_count] is moved towards the batch statistics."""
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check(lib().abcs_dncnn_train_step(plan.handle, _ptr(params), _ptr(adam_m), _ptr(adam_v), _ptr(running),
+                                      int(step), float(lr), _ptr(x_in), _ptr(sigma), _ptr(target), _ptr(loss),
+                                      _ptr(grad), _ptr(workspace), ws_bytes, _stream(stream)))
 
 
 def dct_basis(block):

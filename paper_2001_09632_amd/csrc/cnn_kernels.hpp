@@ -76,14 +76,14 @@ __global__ __launch_bounds__(256) void k_cnn_prep(const float* __restrict__ blob
 __global__ __launch_bounds__(256) void k_cnn_first(const ImgDev* __restrict__ imgs, const CnnTile* __restrict__ tiles,
                                                   int ntiles, const float* __restrict__ v,
                                                   const float* __restrict__ sigma, const float* __restrict__ w1r,
-                                                  const float* __restrict__ blob, unsigned short* __restrict__ act) {
+                                                  const float* __restrict__ b1, unsigned short* __restrict__ act) {
   using namespace cnn;
   constexpr int TH = kTileH + 2, TW = kTileW + 2;
   constexpr int kOutStride = kCh + 8;  // bf16 per staged output pixel
   __shared__ float vin[TH * TW];
   __shared__ __attribute__((aligned(16))) unsigned short obuf[kTileH * kTileW * kOutStride];
   __shared__ float sb[kCh];
-  if (threadIdx.x < kCh) sb[threadIdx.x] = blob[kB1 + threadIdx.x];
+  if (threadIdx.x < kCh) sb[threadIdx.x] = b1[threadIdx.x];
   const int wave = wave_in_group();
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
   // A: weight of output channel 16 cg + n at k = 4 c + g
@@ -153,6 +153,7 @@ __global__ __launch_bounds__(256) void k_cnn_first(const ImgDev* __restrict__ im
 // MODE 0: out = bf16(ReLU(sum + bias)).
 // MODE 1 (input gradient): weights are the transposed, tap-flipped copy,
 //         out = bf16(sum) where mask > 0 (the ReLU of the layer below), else 0.
+// MODE 2: out = bf16(sum) (the pre-normalisation values of DnCNN's layers).
 template <int MODE>
 __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ imgs, const CnnTile* __restrict__ tiles,
                                                 int ntiles, const unsigned short* __restrict__ in,
@@ -246,6 +247,9 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
           if (MODE == 0) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) o[q] = f2bf(fmaxf(acc[r][cg][q] + sbias[c0 + q], 0.f));
+          } else if (MODE == 2) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] = f2bf(acc[r][cg][q]);
           } else {
             const uint2 mk = *(const uint2*)(mask + pix * kCh + c0);
             const unsigned short m4[4] = {(unsigned short)(mk.x & 0xffff), (unsigned short)(mk.x >> 16),
@@ -271,7 +275,7 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
 __global__ __launch_bounds__(256) void k_cnn_last(const ImgDev* __restrict__ imgs, const CnnTile* __restrict__ tiles,
                                                  int ntiles, const float* __restrict__ v,
                                                  const unsigned short* __restrict__ act,
-                                                 const float* __restrict__ w8r, const float* __restrict__ blob,
+                                                 const float* __restrict__ w8r, const float* __restrict__ b8p,
                                                  float* __restrict__ out) {
   using namespace cnn;
   constexpr int TH = kTileH + 2, TW = kTileW + 2;
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(256) void k_cnn_last(const ImgDev* __restrict__ img
   for (int t = threadIdx.x; t < 9 * kCh; t += 256) w8s[t] = f2bf(w8r[t]);
   const int wave = wave_in_group();
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
-  const float b8 = blob[kB8];
+  const float b8 = b8p[0];
   for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
     const CnnTile tl = tiles[ti];
     const ImgDev im = imgs[tl.img];

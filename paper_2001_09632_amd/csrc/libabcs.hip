@@ -8,6 +8,7 @@
 #include "ida_kernels.hpp"
 #include "bm3d_kernels.hpp"
 #include "cnn_kernels.hpp"
+#include "dncnn_kernels.hpp"
 #include "generic_kernels.hpp"
 #include "threshold_kernels.hpp"
 #include "api.cpp.inc"
