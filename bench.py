@@ -185,6 +185,26 @@ def ida_section(dev, weights_path):
     rec["matched_psnr"] = matched
     rec["learned_over_plain_images_per_s"] = round(tp / tl, 2)
 
+    # DnCNN-17 with batch normalisation (the paper's network, trained here by
+    # the library's kernels): the same matched-PSNR rule.
+    dn_path = os.path.join(os.path.dirname(weights_path), "ida_dncnn.npy")
+    if os.path.exists(dn_path):
+        dprm = torch.from_numpy(load_params(dn_path, arch="dncnn")).to(dev)
+        dtrail, dchosen = {}, None
+        for itd in (5, 10, 15, 20, 25, 30):
+            td, xd = timed(itd, "dncnn", dprm)
+            pd_, sd = scores(xd)
+            dtrail[itd] = round(pd_, 3)
+            if dchosen is None and pd_ >= pp - 0.1:
+                dchosen = (itd, td, pd_, sd)
+        if dchosen is None:
+            td, xd = timed(IDA_ITERS, "dncnn", dprm)
+            dchosen = (IDA_ITERS, td) + scores(xd)
+        itd, td, pd_, sd = dchosen
+        rec["dncnn"] = {"denoiser": "dncnn-17", "iters": itd, "images_per_s": round(n / td, 2),
+                        "ms_per_batch": round(td * 1e3, 2), "psnr": round(pd_, 3), "ssim": round(sd, 4),
+                        "psnr_by_iters": dtrail, "over_plain_images_per_s": round(tp / td, 2)}
+
     # The loop variants of Section VI with the learned denoiser at the chosen
     # iteration count: IDA against D-AMP (eq 24) and DAMP-D (eq 27, D_F = 2),
     # and IDA's PSNR as a function of D_F (the sweep of Fig 8).
