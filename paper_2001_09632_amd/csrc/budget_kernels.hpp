@@ -173,7 +173,12 @@ __device__ __forceinline__ T wave_sum_t(T v) {
   return v;
 }
 
-template <typename T>
+// The apportionment runs with 256 threads per image, or with 1024 when a plan
+// holds an image of more than kApBigBlocks blocks (so that the passes over
+// such an image keep many loads in flight).
+constexpr int kApBigBlocks = 8192;
+
+template <int NW, typename T>
 __device__ T group_sum(T v, T* sh) {
   v = wave_sum_t(v);
   const int w = threadIdx.x >> 6;
@@ -182,7 +187,7 @@ __device__ T group_sum(T v, T* sh) {
   __syncthreads();
   T s = 0;
 #pragma unroll
-  for (int i = 0; i < kWavesPerGroup; ++i) s += sh[i];
+  for (int i = 0; i < NW; ++i) s += sh[i];
   return s;
 }
 
@@ -213,11 +218,13 @@ __device__ __forceinline__ int64_t floor_div_exact(int64_t pw, int64_t S) {
   return q;
 }
 
-__global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __restrict__ imgs,
-                                                            int32_t* __restrict__ stat_all,
-                                                            int32_t* __restrict__ k_all,
-                                                            int64_t* __restrict__ off_all) {
-  __shared__ int64_t sh64[kWavesPerGroup];
+template <int kApThreads>
+__global__ __launch_bounds__(kApThreads) void k_apportion(const ImgDev* __restrict__ imgs,
+                                                         int32_t* __restrict__ stat_all,
+                                                         int32_t* __restrict__ k_all,
+                                                         int64_t* __restrict__ off_all) {
+  constexpr int kApWaves = kApThreads / 64;
+  __shared__ int64_t sh64[kApWaves];
   __shared__ int32_t hist[256];
   __shared__ int64_t sel_sh[2];
   const ImgDev im = imgs[blockIdx.x];
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
   const int tid = threadIdx.x;
 
   if (im.mode == kModeZZ) {
-    for (int i = tid; i < nB; i += kGroupThreads) {
+    for (int i = tid; i < nB; i += kApThreads) {
       k[i] = im.kz;
       w[i] = 0;
       off[i] = im.meas_off + (int64_t)i * im.kz;
@@ -241,16 +248,17 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
   // thread t the contiguous range [t per, t per + per).
   const int64_t cap = im.cap;
   int64_t P = im.pool;
-  for (int i = tid; i < nB; i += kGroupThreads) k[i] = -1;  // undecided
+  for (int i = tid; i < nB; i += kApThreads) k[i] = -1;  // undecided
 
   int64_t S = 0;
   bool uniform = false;
   for (;;) {
     int64_t sw = 0, na = 0;
-    for (int i = tid; i < nB; i += kGroupThreads)
+#pragma unroll 4
+    for (int i = tid; i < nB; i += kApThreads)
       if (k[i] < 0) { sw += w[i]; na += 1; }
-    S = group_sum(sw, sh64);
-    const int64_t A = group_sum(na, sh64);
+    S = group_sum<kApWaves>(sw, sh64);
+    const int64_t A = group_sum<kApWaves>(na, sh64);
     if (A == 0) break;
     uniform = (S == 0);
     if (uniform) S = A;
@@ -258,13 +266,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
     // at its cap with the same P and S, then the split is redone.
     const int64_t capS = cap * S;
     int64_t used = 0;
-    for (int i = tid; i < nB; i += kGroupThreads) {
+#pragma unroll 4
+    for (int i = tid; i < nB; i += kApThreads) {
       if (k[i] < 0) {
         const int64_t wi = uniform ? 1 : (int64_t)w[i];
         if (P * wi >= capS) { k[i] = (int32_t)cap; used += cap; }
       }
     }
-    used = group_sum(used, sh64);
+    used = group_sum<kApWaves>(used, sh64);
     if (used == 0) break;
     P -= used;
   }
@@ -272,7 +281,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
   // Floors and remainders of the final split, once: k[i] = floor(P w_i / S),
   // off[i] = remainder (-1 for blocks fixed at the cap).
   int64_t sq = 0;
-  for (int i = tid; i < nB; i += kGroupThreads) {
+#pragma unroll 4
+  for (int i = tid; i < nB; i += kApThreads) {
     if (k[i] < 0) {
       const int64_t wi = uniform ? 1 : (int64_t)w[i];
       const int64_t pw = P * wi;
@@ -284,17 +294,18 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
       off[i] = -1;
     }
   }
-  const int64_t R = P - group_sum(sq, sh64);
+  const int64_t R = P - group_sum<kApWaves>(sq, sh64);
 
   // Radix select of the R-th largest remainder tau (8-bit digits, MSB first).
   int64_t tau = 0, need = R;
   if (R > 0 && S > 1) {
     const int bits = 64 - __clzll((unsigned long long)(S - 1));
     for (int shift = ((bits + 7) / 8) * 8 - 8; shift >= 0; shift -= 8) {
-      hist[tid] = 0;  // kGroupThreads == 256 bins
+      if (tid < 256) hist[tid] = 0;
       __syncthreads();
       const uint64_t hi_mask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
-      for (int i = tid; i < nB; i += kGroupThreads) {
+#pragma unroll 4
+      for (int i = tid; i < nB; i += kApThreads) {
         const int64_t rem = off[i];
         if (rem >= 0 && ((uint64_t)rem & hi_mask) == ((uint64_t)tau & hi_mask))
           atomicAdd(&hist[((uint64_t)rem >> shift) & 255u], 1);
@@ -306,9 +317,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
         sel_sh[0] = 0;
         sel_sh[1] = need;
       }
-      const int32_t bin = hist[255 - tid];
+      const int32_t bin = tid < 256 ? hist[255 - tid] : 0;
       const int64_t above_incl = group_exclusive_scan((int64_t)bin, sh64) + bin;
-      if (above_incl >= need && above_incl - bin < need) {
+      if (tid < 256 && above_incl >= need && above_incl - bin < need) {
         sel_sh[0] = 255 - tid;
         sel_sh[1] = need - (above_incl - bin);
       }
@@ -321,7 +332,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_apportion(const ImgDev* __res
 
   // Final values: floor + 1 for remainders above tau and for the first `need`
   // (by index) remainders equal to tau; then the offsets, both in index order.
-  const int per = (nB + kGroupThreads - 1) / kGroupThreads;
+  const int per = (nB + kApThreads - 1) / kApThreads;
   const int i0 = min(nB, tid * per), i1 = min(nB, i0 + per);
   int64_t neq = 0;
   if (R > 0)
