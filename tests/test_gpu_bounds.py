@@ -199,3 +199,19 @@ def test_threshold_errors():
     small = torch.empty(16, dtype=torch.uint8, device=device())
     with pytest.raises(g.AbcsError, match="ENOSPACE"):
         g.threshold(run.plan, run.px, run.m["thi"], rule="thi", workspace=small)
+
+
+def test_thi_all_zero_image_ties_everywhere():
+    """Every coefficient of a black image is 0: all magnitudes tie, so THI
+    fills blocks in raster order, each in zigzag order."""
+    img = np.zeros((48, 64), np.uint8)
+    px, d = pack_images([img])
+    crs = (0.1, 0.5, 0.9)
+    run = BoundRun(px, [dict(d[0], block=16, subrate=cr, method="zz") for cr in crs]).run()
+    for j, cr in enumerate(crs):
+        _check(run, j, img, 16, cr)
+        m, out = run.image("thi", j)
+        M = int(np.floor(cr * 48 * 64))
+        want = np.minimum(np.maximum(M - 256 * np.arange(12), 0), 256)
+        assert np.array_equal(m, want)
+        assert np.all(out == 0.0)
