@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # dense bf16 matrix-core peak of MI355X
 SEEDS = list(range(1000, 1064))
 SUBRATES = (0.1, 0.2, 0.3, 0.4, 0.5)
 METHODS = ("bbv", "dd")
@@ -185,6 +186,32 @@ def ida_section(dev, weights_path):
     rec["matched_psnr"] = matched
     rec["learned_over_plain_images_per_s"] = round(tp / tl, 2)
 
+    # Roofline of the learned denoisers alone (one abcs_denoise call on the
+    # batch, HIP events on the launch stream): algorithmic flops of the
+    # convolutions (2 x 9 x C_in x C_out per pixel and layer) against the
+    # dense bf16 matrix-core peak.
+    def denoise_ms(den, params, reps=5):
+        ws = torch.empty(g.denoise_workspace_bytes(plan, den), dtype=torch.uint8, device=dev)
+        sig = torch.full((n,), 25.0, dtype=torch.float32, device=dev)
+        o = torch.empty(plan.pixels, dtype=torch.float32, device=dev)
+        g.denoise(plan, io, sig, o, den, params=params, workspace=ws)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            g.denoise(plan, io, sig, o, den, params=params, workspace=ws)
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    def conv_roofline(ms, n_mid):
+        flop = plan.pixels * 2 * 9 * (2 * 64 + n_mid * 64 * 64 + 64)
+        ach = flop / (ms * 1e-3) / 1e12
+        return {"ms_per_call": round(ms, 3), "bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4), "algorithmic_flop": int(flop)}
+
+    rec["denoiser_roofline"] = {"cnn": conv_roofline(denoise_ms("cnn", prm), 6),
+                                "bm3d_ms_per_call": round(denoise_ms("bm3d", None, reps=2), 3)}
+
     # DnCNN-17 with batch normalisation (the paper's network, trained here by
     # the library's kernels): the same matched-PSNR rule.
     dn_path = os.path.join(os.path.dirname(weights_path), "ida_dncnn.npy")
@@ -204,6 +231,7 @@ def ida_section(dev, weights_path):
         rec["dncnn"] = {"denoiser": "dncnn-17", "iters": itd, "images_per_s": round(n / td, 2),
                         "ms_per_batch": round(td * 1e3, 2), "psnr": round(pd_, 3), "ssim": round(sd, 4),
                         "psnr_by_iters": dtrail, "over_plain_images_per_s": round(tp / td, 2)}
+        rec["denoiser_roofline"]["dncnn"] = conv_roofline(denoise_ms("dncnn", dprm), 15)
 
     # The loop variants of Section VI with the learned denoiser at the chosen
     # iteration count: IDA against D-AMP (eq 24) and DAMP-D (eq 27, D_F = 2),
