@@ -485,6 +485,63 @@ def wht_section(dev, px, images, out_dct):
                               for xf, tab in (("wht", pw), ("dct", pd)) for i, m in enumerate(METHODS)}}
 
 
+def train_section(dev, batch=32, steps=10):
+    """Training steps of both learned denoisers on a batch of 32 synthetic
+    128x128 crops with Gaussian noise (sigma 25): crops/s and the matrix-core
+    roofline of a step (forward + input and weight gradients = 3 x the
+    forward convolution flops)."""
+    import numpy as np
+    import torch
+    import paper_2001_09632_amd as g
+    from paper_2001_09632_amd.train import he_init, dncnn_init
+    import synth
+    crop = 128
+    plan = g.Plan([dict(height=crop, width=crop, block=16, subrate=0.25, method="zz", pixel_offset=0)
+                   for _ in range(batch)])
+    clean = np.stack([synth.synth_image(5000 + i, crop, crop).astype(np.float32) for i in range(batch)])
+    rng = np.random.default_rng(12)
+    x = torch.from_numpy((clean + rng.normal(0, 25, clean.shape)).astype(np.float32).reshape(-1)).to(dev)
+    t = torch.from_numpy(clean.reshape(-1)).to(dev)
+    sig = torch.full((batch,), 25.0, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    out = {}
+    for name, n_mid in (("cnn", 6), ("dncnn", 15)):
+        if name == "cnn":
+            prm = torch.from_numpy(he_init(0)).to(dev)
+            run = None
+            ws = torch.empty(g.cnn_train_workspace_bytes(plan), dtype=torch.uint8, device=dev)
+        else:
+            b0, r0 = dncnn_init(0)
+            prm = torch.from_numpy(b0).to(dev)
+            run = torch.from_numpy(r0).to(dev)
+            ws = torch.empty(g.dncnn_train_workspace_bytes(plan), dtype=torch.uint8, device=dev)
+        m, v = torch.zeros_like(prm), torch.zeros_like(prm)
+
+        def step(k):
+            if run is None:
+                g.cnn_train_step(plan, prm, m, v, k, 1e-4, x, sig, t, loss, workspace=ws)
+            else:
+                g.dncnn_train_step(plan, prm, m, v, run, k, 1e-4, x, sig, t, loss, workspace=ws)
+
+        for k in range(1, 4):
+            step(k)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for k in range(4, 4 + steps):
+            step(k)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / steps
+        flop = 3 * plan.pixels * 2 * 9 * (2 * 64 + n_mid * 64 * 64 + 64)
+        ach = flop / (ms * 1e-3) / 1e12
+        out[name] = {"ms_per_step": round(ms, 3), "crops_per_s": round(batch / (ms * 1e-3), 1),
+                     "roofline": {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4)}}
+    out["batch"] = f"{batch} x {crop}x{crop} crops"
+    return out
+
+
 def cpu_baseline(images, n_images, deadline_s=30.0):
     """The FP64 oracle (budget + sensing + decoding) on the first n_images of
     the batch at every (estimator, subrate) pair; single-threaded numpy."""
@@ -518,6 +575,7 @@ def main():
     ap.add_argument("--no-ida", action="store_true")
     ap.add_argument("--no-bounds", action="store_true", help="skip the THI / THB bounds section")
     ap.add_argument("--no-wht", action="store_true", help="skip the Walsh-Hadamard section")
+    ap.add_argument("--no-train", action="store_true", help="skip the denoiser training-step section")
     ap.add_argument("--cnn-weights", default=os.path.join(ROOT, "paper_2001_09632_amd", "weights", "ida_cnn.npy"))
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a device-to-device copy of this many MiB (5 times) and exit; "
@@ -629,6 +687,11 @@ def main():
         log("wht")
         wht = wht_section(dev, px, images, out32)
 
+    train = None
+    if not args.no_train:
+        log("train")
+        train = train_section(dev)
+
     ida = None
     if not args.no_ida:
         log("ida")
@@ -667,6 +730,7 @@ def main():
         "cpu_baseline": cpu,
         "bounds": bounds,
         "wht": wht,
+        "train": train,
         "ida": ida,
         "stream": stream,
     }

@@ -380,10 +380,20 @@ __global__ __launch_bounds__(256) void k_cnn_loss(const float* __restrict__ out,
 }
 
 // Sum `n` float64 partials in order into out[0] (single thread; n is small).
-__global__ void k_sum_loss(const double* __restrict__ part, int64_t n, int64_t pixels, float* __restrict__ loss) {
+// loss = sum of the n partials / pixels; one workgroup of 256 threads: thread
+// t sums partials t, t + 256, ..., then a fixed tree (deterministic).
+__global__ __launch_bounds__(256) void k_sum_loss(const double* __restrict__ part, int64_t n, int64_t pixels,
+                                                  float* __restrict__ loss) {
+  __shared__ double sh[256];
   double s = 0.0;
-  for (int64_t i = 0; i < n; ++i) s += part[i];
-  loss[0] = (float)(s / (double)pixels);
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] = (float)(sh[0] / (double)pixels);
 }
 
 // Layer-8 input gradient: dz7[q][c] = [a7[q][c] > 0] sum_tap w8[tap][c] df[q - off(tap)].
@@ -428,78 +438,85 @@ __global__ __launch_bounds__(256) void k_cnn_last_bwd(const ImgDev* __restrict__
 
 // Weight and bias gradients of layer 8 (64 -> 1):
 //   dW8[tap][c] = sum_p df[p] a7[p + off(tap)][c],  db8 = sum_p df[p].
-// Thread t of a workgroup owns outputs t, t + 256, t + 512 of the 577 and
-// walks the workgroup's pixel range; partial sums go to part[wg][577].
+// Workgroups loop over 8 x 16-pixel tiles; thread t owns channel c = t % 64
+// and every fourth pixel of a tile (t / 64 = 0..3), keeping 9 + 1 sums; the
+// four pixel phases are added in a fixed order at the end and the
+// workgroup's partial sums go to part[wg][577] (tap * 64 + c, then db8).
 __global__ __launch_bounds__(256) void k_cnn_last_wgrad(const ImgDev* __restrict__ imgs,
-                                                       const int32_t* __restrict__ pix_img, int64_t pixels,
+                                                       const CnnTile* __restrict__ tiles, int ntiles,
                                                        const float* __restrict__ df,
                                                        const unsigned short* __restrict__ a7,
-                                                       float* __restrict__ part, int64_t chunk) {
+                                                       float* __restrict__ part) {
   using namespace cnn;
-  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(pixels, p0 + chunk);
-  float acc[3] = {0.f, 0.f, 0.f};
-  for (int64_t p = p0; p < p1; ++p) {
-    const ImgDev im = imgs[pix_img[p >> kPixChunkShift]];
-    const int64_t lp = p - im.out_off;
-    const int y = (int)(lp / im.Wc), x = (int)(lp - (int64_t)y * im.Wc);
-    const float dv = df[p];
+  __shared__ float sh[4][9 * 64 + 1];
+  const int c = threadIdx.x & 63, pq = threadIdx.x >> 6;
+  float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const CnnTile tl = tiles[ti];
+    const ImgDev im = imgs[tl.img];
+    for (int px = pq; px < kTileH * kTileW; px += 4) {
+      const int y = tl.y0 + px / kTileW, x = tl.x0 + px % kTileW;
+      const float dv = df[im.out_off + (int64_t)y * im.Wc + x];
+      bacc += dv;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int o = threadIdx.x + 256 * k;
-      if (o < 576) {
-        const int tap = o / 64, c = o % 64;
+      for (int tap = 0; tap < 9; ++tap) {
         const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
         if (yy >= 0 && yy < im.Hc && xx >= 0 && xx < im.Wc)
-          acc[k] = fmaf(dv, bf2f(a7[(im.out_off + (int64_t)yy * im.Wc + xx) * kCh + c]), acc[k]);
-      } else if (o == 576) {
-        acc[k] += dv;
+          acc[tap] = fmaf(dv, bf2f(a7[(im.out_off + (int64_t)yy * im.Wc + xx) * kCh + c]), acc[tap]);
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int o = threadIdx.x + 256 * k;
-    if (o <= 576) part[(int64_t)blockIdx.x * 577 + o] = acc[k];
-  }
+  for (int tap = 0; tap < 9; ++tap) sh[pq][tap * 64 + c] = acc[tap];
+  if (c == 0) sh[pq][576] = bacc;
+  __syncthreads();
+  for (int o = threadIdx.x; o < 577; o += 256)
+    part[(int64_t)blockIdx.x * 577 + o] = ((sh[0][o] + sh[1][o]) + sh[2][o]) + sh[3][o];
 }
 
 // Weight and bias gradients of layer 1 (2 -> 64) from dz1 and the network
 // input [v / 255, min(sigma, 255) / 255] (zero outside the image):
-// 64 x 9 x 2 weights + 64 biases = 1216 outputs, same scheme as above.
+// 64 x 9 x 2 weights (co * 18 + tap * 2 + c) + 64 biases = 1216 outputs.
+// Same scheme as k_cnn_last_wgrad: thread t owns output channel co = t % 64
+// and every fourth pixel of each tile, with 18 + 1 sums.
 __global__ __launch_bounds__(256) void k_cnn_first_wgrad(const ImgDev* __restrict__ imgs,
-                                                        const int32_t* __restrict__ pix_img, int64_t pixels,
+                                                        const CnnTile* __restrict__ tiles, int ntiles,
                                                         const float* __restrict__ v, const float* __restrict__ sigma,
                                                         const unsigned short* __restrict__ dz1,
-                                                        float* __restrict__ part, int64_t chunk) {
+                                                        float* __restrict__ part) {
   using namespace cnn;
-  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(pixels, p0 + chunk);
-  float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int64_t p = p0; p < p1; ++p) {
-    const int ii = pix_img[p >> kPixChunkShift];
-    const ImgDev im = imgs[ii];
-    const int64_t lp = p - im.out_off;
-    const int y = (int)(lp / im.Wc), x = (int)(lp - (int64_t)y * im.Wc);
-    const float s = fminf(sigma[ii], 255.f) * (1.f / 255.f);
+  __shared__ float sh[4][1216];
+  const int co = threadIdx.x & 63, pq = threadIdx.x >> 6;
+  float acc[18];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int o = threadIdx.x + 256 * k;
-      if (o < 1152) {
-        const int co = o / 18, tap = (o % 18) / 2, c = o % 2;
+  for (int k = 0; k < 18; ++k) acc[k] = 0.f;
+  float bacc = 0.f;
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const CnnTile tl = tiles[ti];
+    const ImgDev im = imgs[tl.img];
+    const float s = fminf(sigma[tl.img], 255.f) * (1.f / 255.f);
+    for (int px = pq; px < kTileH * kTileW; px += 4) {
+      const int y = tl.y0 + px / kTileW, x = tl.x0 + px % kTileW;
+      const int64_t p = im.out_off + (int64_t)y * im.Wc + x;
+      const float gz = bf2f(dz1[p * kCh + co]);
+      bacc += gz;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
         const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
         if (yy >= 0 && yy < im.Hc && xx >= 0 && xx < im.Wc) {
-          const float in = c == 0 ? v[im.out_off + (int64_t)yy * im.Wc + xx] * (1.f / 255.f) : s;
-          acc[k] = fmaf(bf2f(dz1[p * kCh + co]), in, acc[k]);
+          acc[2 * tap] = fmaf(gz, v[im.out_off + (int64_t)yy * im.Wc + xx] * (1.f / 255.f), acc[2 * tap]);
+          acc[2 * tap + 1] = fmaf(gz, s, acc[2 * tap + 1]);
         }
-      } else if (o < 1216) {
-        acc[k] += bf2f(dz1[p * kCh + (o - 1152)]);
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const int o = threadIdx.x + 256 * k;
-    if (o < 1216) part[(int64_t)blockIdx.x * 1216 + o] = acc[k];
-  }
+  for (int k = 0; k < 18; ++k) sh[pq][co * 18 + k] = acc[k];
+  sh[pq][1152 + co] = bacc;
+  __syncthreads();
+  for (int o = threadIdx.x; o < 1216; o += 256)
+    part[(int64_t)blockIdx.x * 1216 + o] = ((sh[0][o] + sh[1][o]) + sh[2][o]) + sh[3][o];
 }
 
 // Weight and bias gradients of a 64 -> 64 layer on bfloat16 MFMA:
@@ -597,8 +614,26 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ par
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= len) return;
   float s = 0.f;
+#pragma unroll 8
   for (int w = 0; w < nparts; ++w) s += part[(int64_t)w * stride + i];
   out[i] = s;
+}
+
+// The same sum for few outputs and many partials: one workgroup per output,
+// thread t adds partials t, t + 256, ..., then a fixed tree.
+__global__ __launch_bounds__(256) void k_sum_parts_wide(const float* __restrict__ part, int nparts, int64_t stride,
+                                                       float* __restrict__ out) {
+  __shared__ float sh[256];
+  const int64_t i = blockIdx.x;
+  float s = 0.f;
+  for (int w = threadIdx.x; w < nparts; w += 256) s += part[(int64_t)w * stride + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = sh[0];
 }
 
 // Adam with bias correction: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,

@@ -107,13 +107,22 @@ __global__ __launch_bounds__(256) void k_bn_sums(const unsigned short* __restric
   }
 }
 
-// out[i] = sum over w < nparts of part[w * 128 + i], i < 128 (fixed order).
-__global__ void k_bn_reduce(const double* __restrict__ part, int nparts, double* __restrict__ out) {
-  const int i = threadIdx.x;
-  if (i >= 128) return;
+// out[i] = sum over w < nparts of part[w * 128 + i], i < 128, in a fixed
+// order: one workgroup per output, thread t adds partials t, t + 256, ...,
+// then a fixed tree.
+__global__ __launch_bounds__(256) void k_bn_reduce(const double* __restrict__ part, int nparts,
+                                                  double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int i = blockIdx.x;
   double s = 0.0;
-  for (int w = 0; w < nparts; ++w) s += part[(int64_t)w * 128 + i];
-  out[i] = s;
+  for (int w = threadIdx.x; w < nparts; w += 256) s += part[(int64_t)w * 128 + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = sh[0];
 }
 
 // Training-mode normalisation: mean and biased variance from the sums, then
