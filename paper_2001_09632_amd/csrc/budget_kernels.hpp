@@ -56,20 +56,27 @@ __global__ __launch_bounds__(kGroupThreads) void k_bbv_stats(const ImgDev* __res
 }
 
 // ---------------------------------------------------------------------------
-// DD n_i: one wavefront per tile of 16x16 blocks.  The float32 MFMA transform
-// decides |c| > T for every coefficient further than kDDGuard from T; the rest
-// are recomputed in float64 in the fixed order of dct16_coef_f64 from the
-// block staged in LDS.
+// DD n_i: one wavefront per tile of 16x16 blocks.  A compensated float16
+// MFMA transform (dct16_fwd_f16k32) decides |c| > T for every coefficient
+// further than kDDGuard from T; the rest are recomputed in float64 in the
+// fixed order of dct16_coef_f64 from the block staged in LDS, so the counts
+// are those of the float64 definition whatever the screening arithmetic.
 //
-// kDDGuard bounds the float32 error of a coefficient.  With |X| <= 255 and
-// sum_j |D[v][j]| <= sqrt(16) = 4, the first product is a 16-term sum of
-// magnitude <= 1020 and errs by <= (16 + 1) 2^-24 1020 ~ 1.1e-3 (accumulation
-// plus the rounding of D to float32); the second adds 16 terms weighted by
-// |D| <= 4 in total: <= 4 * 1.1e-3 + (16 + 1) 2^-24 * 4 * 1020 ~ 8.4e-3.  The
-// guard is 2.4x that, enough even if every step rounded with twice the unit
-// roundoff.
+// kDDGuard bounds the screening error of a coefficient (u = 2^-24 the float32
+// unit roundoff, with every float32 sum of n terms taken to err by at most
+// n u times the sum of their magnitudes).  Pixels are exact in float16; the
+// basis split D = Dhi + Dlo leaves at most 8.4e-8 per entry (|D| <= 0.354,
+// float16 unit roundoff 2^-11, subnormal spacing 2^-24).  With |X| <= 255 and
+// sum_j |D[v][j]| <= sqrt(16) = 4:
+//   stage 1, 32 products of magnitude sum <= 1020.1: 32 u 1020.1 + 16 * 255 *
+//     8.4e-8 <= 2.3e-3;
+//   stage 2, 48 products of magnitude sum <= 4087: 48 u 4087 = 1.17e-2, plus
+//     the stage-1 error times 4 (9.2e-3), the rounding of Tl (|T - Th| <=
+//     0.5, 4 * 2.4e-4), the dropped Dlo Tl (16 * 1.73e-4 * 0.5 = 1.4e-3) and
+//     the basis residual on T (16 * 8.4e-8 * 1020.5 = 1.4e-3): <= 2.5e-2.
+// The guard is twice that.
 // ---------------------------------------------------------------------------
-constexpr float kDDGuard = 0.02f;
+constexpr float kDDGuard = 0.05f;
 // Undecided coefficients are queued per wave and settled in float64 in
 // batches of 64.  A block adds at most m1 <= 128 (C_F >= 1), so the queue is
 // flushed before a block whenever fewer than 128 slots are free.
@@ -107,6 +114,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_dd_stats(const ImgDev* __rest
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane16_init(L);
+  Lane16K32 K;
+  lane16k32_init(K, L);
   const int lane = threadIdx.x & 63;
   const float T = (float)im.T;
   const int m1 = im.m1 < 128 ? im.m1 : 128;
@@ -120,6 +129,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_dd_stats(const ImgDev* __rest
   wave_lds_sync();
   int32_t my_stat = 0;  // lane b keeps block b's count of coefficients decided in float32
   int nlist = 0;        // wave-uniform length of the queue
+  // Lanes whose coefficient r is among the first m1 in zigzag order; the
+  // decisions below are wave masks, so each costs two compares per register.
+  uint64_t inm[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) inm[r] = __ballot(L.zr[r] < m1);
+  const float t_hi = T + kDDGuard, t_lo = T - kDDGuard;
 #pragma unroll 2
   for (int b = 0; b < kTileBlocks; ++b) {
     if (nlist > kDDListCap - 128) {
@@ -130,21 +145,27 @@ __global__ __launch_bounds__(kGroupThreads) void k_dd_stats(const ImgDev* __rest
     float a[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) a[c] = (float)((pw >> (8 * c)) & 0xffu);
-    const f32x4 C = dct16_fwd(a, L);
+    const f32x4 C = dct16_fwd_f16k32(a, K);
     int cnt = 0;
+    uint64_t un[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float av = fabsf(C[r]);
-      const bool in = L.zr[r] < m1;
-      const bool above = in && (av > T + kDDGuard);
-      const bool unsure = in && !above && (av >= T - kDDGuard);
-      cnt += __popcll(__ballot(above));
-      const uint64_t um = __ballot(unsure);
-      if (um != 0) {
-        const int pos = nlist + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(um >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)um, 0u));
-        if (unsure) list[pos] = (uint16_t)((b << 8) | ((4 * L.g + r) << 4) | L.n);
-        nlist += __popcll(um);
+      const uint64_t gt = __ballot(av > t_hi);
+      const uint64_t ge = __ballot(av >= t_lo);
+      cnt += __popcll(gt & inm[r]);
+      un[r] = ge & ~gt & inm[r];
+    }
+    if ((un[0] | un[1] | un[2] | un[3]) != 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint64_t um = un[r];
+        if (um != 0) {
+          const int pos = nlist + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(um >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)um, 0u));
+          if ((um >> lane) & 1) list[pos] = (uint16_t)((b << 8) | ((4 * L.g + r) << 4) | L.n);
+          nlist += __popcll(um);
+        }
       }
     }
     if (lane == b) my_stat = cnt;

@@ -156,6 +156,53 @@ __device__ __forceinline__ f32x4 dct16_fwd_p(const float a[4], const Lane16P<P>&
   return out;
 }
 
+// Compensated float16 forward transform with the hi and lo halves of each
+// product packed into one K = 32 MFMA (v_mfma_f32_16x16x32_f16; lane
+// l = 16g + n supplies K slots 8g .. 8g+7, slot c < 4 carrying index 4g + c
+// of the hi term and slot 4 + c the same index of the lo term):
+//   T = [X | X] [Dhi ; Dlo],   C = [Dhi | Dhi] [Th ; Tl] + [Dlo | 0] [Th ; Tl],
+// the same five products as dct16_fwd_p<kPrecFP16x3> in three instructions.
+// The two products of C are one accumulation chain of a single opcode: with
+// a 16x16x16 instruction accumulating straight onto the 16x16x32 result the
+// compiler emitted the pair back to back and the sums came out wrong.
+// The operands are assembled from whole 4-wide vectors with shufflevector:
+// filling the 8-wide vectors element by element from the bits of a u16x4 was
+// also compiled wrongly (every slot got element 0).  Layout as dct16_fwd.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+struct Lane16K32 {
+  f16x8 d_hilo;  // slots: Dhi[n][4g+c], then Dlo[n][4g+c]
+  f16x8 d_hihi;  // slots: Dhi[n][4g+c] twice
+  f16x8 d_lo0;   // slots: Dlo[n][4g+c], then zero
+};
+
+__device__ __forceinline__ void lane16k32_init(Lane16K32& K, const Lane16& L) {
+  u16x4 hi, lo;
+  split16<false>(L.dR, hi, lo);
+  const f16x4 h = __builtin_bit_cast(f16x4, hi), l = __builtin_bit_cast(f16x4, lo);
+  const f16x4 z = {0, 0, 0, 0};
+  K.d_hilo = __builtin_shufflevector(h, l, 0, 1, 2, 3, 4, 5, 6, 7);
+  K.d_hihi = __builtin_shufflevector(h, h, 0, 1, 2, 3, 0, 1, 2, 3);
+  K.d_lo0 = __builtin_shufflevector(l, z, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+__device__ __forceinline__ f32x4 dct16_fwd_f16k32(const float a[4], const Lane16K32& K) {
+  u16x4 xh;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) xh[c] = to16<false>(a[c]);
+  const f16x4 x4 = __builtin_bit_cast(f16x4, xh);
+  const f16x8 x = __builtin_shufflevector(x4, x4, 0, 1, 2, 3, 0, 1, 2, 3);
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  const f32x4 t = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, K.d_hilo, zero, 0, 0, 0);
+  const float tv[4] = {t[0], t[1], t[2], t[3]};
+  u16x4 th, tl;
+  split16<false>(tv, th, tl);
+  const f16x8 tt = __builtin_shufflevector(__builtin_bit_cast(f16x4, th), __builtin_bit_cast(f16x4, tl), 0, 1, 2, 3,
+                                           4, 5, 6, 7);
+  const f32x4 out = __builtin_amdgcn_mfma_f32_16x16x32_f16(K.d_hihi, tt, zero, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(K.d_lo0, tt, out, 0, 0, 0);
+}
+
 // Inverse: in e[c] = C[4g+c][n], out X[n][4g+r].
 template <int P>
 __device__ __forceinline__ f32x4 idct16_inv_p(const float e[4], const Lane16P<P>& H) {
