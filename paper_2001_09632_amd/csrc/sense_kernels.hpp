@@ -25,7 +25,9 @@ struct WaveLds {
 // y[off_i + z] = C_i[zigzag[z]] for z < k_i.  The transform output goes to
 // LDS at its zigzag rank and leaves with unit-stride stores of the block's k_i
 // coefficients (slot z of store q is lane + 64 q); slots at or beyond k_i get
-// an out-of-range offset and are dropped.
+// an out-of-range offset and are dropped.  Blocks are taken in pairs, so that
+// the matrix cores always have two independent product chains of the wave to
+// work on.
 template <int P>
 __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restrict__ imgs,
                                                           const Tile* __restrict__ tiles, int ntiles,
@@ -33,7 +35,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
                                                           const int32_t* __restrict__ k_all,
                                                           const int64_t* __restrict__ off_all,
                                                           float* __restrict__ y) {
-  __shared__ WaveLds lds[kWavesPerGroup];
+  __shared__ WaveLds lds[kWavesPerGroup][2];
   __shared__ PxStage stage[kWavesPerGroup];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
@@ -45,29 +47,38 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
   if (P != kPrecFP32) lane16p_init(H, L);
   TileIO io;
   tile_io_init(io, im, tl, px, y, k_all, off_all, L);
-  float* buf = lds[wave_in_group()].c;
+  float* buf[2] = {lds[wave_in_group()][0].c, lds[wave_in_group()][1].c};
   uint32_t* st = stage[wave_in_group()].w;
   const int lane = threadIdx.x & 63;
   stage_tile_px(io, im.pitch, tl.count, st);
   wave_lds_sync();
 #pragma unroll
-  for (int b = 0; b < kTileBlocks; ++b) {
-    const uint32_t pw = staged_px(st, b, L);
-    float a[4];
+  for (int b0 = 0; b0 < kTileBlocks; b0 += 2) {
+    f32x4 C[2];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a[c] = (float)((pw >> (8 * c)) & 0xffu);
-    const f32x4 C = P == kPrecFP32 ? dct16_fwd(a, L) : dct16_fwd_p<P>(a, H);
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t pw = staged_px(st, b0 + h, L);
+      float a[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) buf[L.zr[r]] = C[r];
+      for (int c = 0; c < 4; ++c) a[c] = (float)((pw >> (8 * c)) & 0xffu);
+      C[h] = P == kPrecFP32 ? dct16_fwd(a, L) : dct16_fwd_p<P>(a, H);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[h][L.zr[r]] = C[h][r];
     wave_lds_sync();
-    const int kk = __builtin_amdgcn_readlane(io.k, b);
-    const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(io.rel_lo, b);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (64 * q < kk) {
-        const int z = lane + 64 * q;
-        const uint32_t voff = z < kk ? rel4 + 4u * (uint32_t)z : 0xffffffffu;
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(buf[z]), io.y, voff, 0, 0);
+    for (int h = 0; h < 2; ++h) {
+      const int kk = __builtin_amdgcn_readlane(io.k, b0 + h);
+      const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(io.rel_lo, b0 + h);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (64 * q < kk) {
+          const int z = lane + 64 * q;
+          const uint32_t voff = z < kk ? rel4 + 4u * (uint32_t)z : 0xffffffffu;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(buf[h][z]), io.y, voff, 0, 0);
+        }
       }
     }
     wave_lds_sync();
