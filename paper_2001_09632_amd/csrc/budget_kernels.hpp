@@ -194,10 +194,9 @@ __device__ __forceinline__ T wave_sum_t(T v) {
   return v;
 }
 
-// The apportionment runs with 256 threads per image, or with 1024 when a plan
-// holds an image of more than kApBigBlocks blocks (so that the passes over
-// such an image keep many loads in flight).
-constexpr int kApBigBlocks = 8192;
+// k_apportion keeps an image's blocks in global memory; it serves images of
+// more than 8192 blocks (1024 threads per image).  Smaller images use
+// k_apportion_reg below, which holds them in registers.
 
 template <int NW, typename T>
 __device__ T group_sum(T v, T* sh) {
@@ -381,6 +380,157 @@ __global__ __launch_bounds__(kApThreads) void k_apportion(const ImgDev* __restri
     off[i] = base;
     base += k[i];
   }
+}
+
+// The same apportionment with each image's blocks held in registers: thread
+// t owns blocks [t kPer, t kPer + kPer), so every pass (the cap loop, the
+// floors, the radix select, the ties and the offsets) works on registers and
+// LDS only, and global memory is read once and written once.  For images of
+// at most kThreads * kPer blocks; the steps and their results are those of
+// k_apportion.
+template <int kThreads, int kPer>
+__global__ __launch_bounds__(kThreads) void k_apportion_reg(const ImgDev* __restrict__ imgs,
+                                                            int32_t* __restrict__ stat_all,
+                                                            int32_t* __restrict__ k_all,
+                                                            int64_t* __restrict__ off_all) {
+  constexpr int kWaves = kThreads / 64;
+  __shared__ int64_t sh64[kWaves];
+  __shared__ int32_t hist[256];
+  __shared__ int64_t sel_sh[2];
+  const ImgDev im = imgs[blockIdx.x];
+  const int nB = im.nB;
+  int32_t* wg = stat_all + im.blk_off;
+  int32_t* kg = k_all + im.blk_off;
+  int64_t* og = off_all + im.blk_off;
+  const int tid = threadIdx.x;
+  const int i0 = tid * kPer;
+
+  if (im.mode == kModeZZ) {
+    for (int i = tid; i < nB; i += kThreads) {
+      kg[i] = im.kz;
+      wg[i] = 0;
+      og[i] = im.meas_off + (int64_t)i * im.kz;
+    }
+    return;
+  }
+
+  // kv: -1 undecided, else the block's share; blocks past nB are fixed at 0
+  // and carry no remainder.
+  int32_t wv[kPer], kv[kPer];
+  int64_t rem[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const bool valid = i0 + j < nB;
+    wv[j] = valid ? wg[i0 + j] : 0;
+    kv[j] = valid ? -1 : 0;
+    rem[j] = -1;
+  }
+  const int64_t cap = im.cap;
+  int64_t P = im.pool;
+  int64_t S = 0;
+  bool uniform = false;
+  for (;;) {
+    int64_t sw = 0, na = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+      if (kv[j] < 0) {
+        sw += wv[j];
+        na += 1;
+      }
+    S = group_sum<kWaves>(sw, sh64);
+    const int64_t A = group_sum<kWaves>(na, sh64);
+    if (A == 0) break;
+    uniform = (S == 0);
+    if (uniform) S = A;
+    const int64_t capS = cap * S;
+    int64_t used = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+      if (kv[j] < 0) {
+        const int64_t wi = uniform ? 1 : (int64_t)wv[j];
+        if (P * wi >= capS) {
+          kv[j] = (int32_t)cap;
+          used += cap;
+        }
+      }
+    used = group_sum<kWaves>(used, sh64);
+    if (used == 0) break;
+    P -= used;
+  }
+
+  int64_t sq = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j)
+    if (kv[j] < 0) {
+      const int64_t wi = uniform ? 1 : (int64_t)wv[j];
+      const int64_t pw = P * wi;
+      const int64_t q = floor_div_exact(pw, S);
+      kv[j] = (int32_t)q;
+      rem[j] = pw - q * S;
+      sq += q;
+    }
+  const int64_t R = P - group_sum<kWaves>(sq, sh64);
+
+  int64_t tau = 0, need = R;
+  if (R > 0 && S > 1) {
+    const int bits = 64 - __clzll((unsigned long long)(S - 1));
+    for (int shift = ((bits + 7) / 8) * 8 - 8; shift >= 0; shift -= 8) {
+      if (tid < 256) hist[tid] = 0;
+      __syncthreads();
+      const uint64_t hi_mask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
+#pragma unroll
+      for (int j = 0; j < kPer; ++j)
+        if (rem[j] >= 0 && ((uint64_t)rem[j] & hi_mask) == ((uint64_t)tau & hi_mask))
+          atomicAdd(&hist[((uint64_t)rem[j] >> shift) & 255u], 1);
+      __syncthreads();
+      if (tid == 0) {
+        sel_sh[0] = 0;
+        sel_sh[1] = need;
+      }
+      const int32_t bin = tid < 256 ? hist[255 - tid] : 0;
+      const int64_t above_incl = group_exclusive_scan((int64_t)bin, sh64) + bin;
+      if (tid < 256 && above_incl >= need && above_incl - bin < need) {
+        sel_sh[0] = 255 - tid;
+        sel_sh[1] = need - (above_incl - bin);
+      }
+      __syncthreads();
+      tau |= (int64_t)sel_sh[0] << shift;
+      need = sel_sh[1];
+      __syncthreads();
+    }
+  }
+
+  int64_t neq = 0;
+  if (R > 0) {
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) neq += (rem[j] == tau) ? 1 : 0;
+  }
+  int64_t rank = group_exclusive_scan(neq, sh64);
+  const int32_t add = (im.mode == kModeDD) ? im.m1 : 0;
+  int64_t ksum = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    int64_t ki = kv[j];
+    if (R > 0 && rem[j] >= 0) {
+      if (rem[j] > tau) {
+        ki += 1;
+      } else if (rem[j] == tau) {
+        if (rank < need) ki += 1;
+        rank += 1;
+      }
+    }
+    ki += add;
+    kv[j] = (int32_t)ki;
+    if (i0 + j < nB) ksum += ki;
+  }
+  int64_t base = group_exclusive_scan(ksum, sh64) + im.meas_off;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j)
+    if (i0 + j < nB) {
+      kg[i0 + j] = kv[j];
+      og[i0 + j] = base;
+      base += kv[j];
+    }
 }
 
 }  // namespace abcs
