@@ -14,11 +14,9 @@ namespace abcs {
 // column of the block to the right, or the block's own last row / column at
 // the image edge.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kGroupThreads) void k_bbv_stats(const ImgDev* __restrict__ imgs,
-                                                            const Tile* __restrict__ tiles, int ntiles,
-                                                            const uint8_t* __restrict__ px,
-                                                            int32_t* __restrict__ stat) {
-  const int t = blockIdx.x * kGroupThreads + threadIdx.x;
+__device__ __forceinline__ void bbv_stats_thread(const ImgDev* __restrict__ imgs, const Tile* __restrict__ tiles,
+                                                 int ntiles, const uint8_t* __restrict__ px,
+                                                 int32_t* __restrict__ stat, int t) {
   const int ti = t / kTileBlocks, b = t % kTileBlocks;
   if (ti >= ntiles) return;
   const Tile tl = tiles[ti];
@@ -98,17 +96,16 @@ __device__ __forceinline__ void dd_flush(const uint16_t* list, int n, const uint
   wave_lds_sync();
 }
 
-__global__ __launch_bounds__(kGroupThreads) void k_dd_stats(const ImgDev* __restrict__ imgs,
-                                                           const Tile* __restrict__ tiles, int ntiles,
-                                                           const uint8_t* __restrict__ px,
-                                                           int32_t* __restrict__ stat) {
+__device__ __forceinline__ void dd_stats_group(const ImgDev* __restrict__ imgs, const Tile* __restrict__ tiles,
+                                               int ntiles, const uint8_t* __restrict__ px,
+                                               int32_t* __restrict__ stat, int group) {
   __shared__ double sD[256];
   __shared__ PxStage stage[kWavesPerGroup];
   __shared__ uint16_t ulist[kWavesPerGroup][kDDListCap];
   __shared__ int32_t ucount[kWavesPerGroup][kTileBlocks];
   sD[threadIdx.x] = c_D16d[threadIdx.x];
   __syncthreads();
-  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  const int wave = group * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
   const Tile tl = tiles[wave];
   const ImgDev im = imgs[tl.img];
@@ -173,6 +170,21 @@ __global__ __launch_bounds__(kGroupThreads) void k_dd_stats(const ImgDev* __rest
   if (nlist > 0) dd_flush(list, nlist, st, sD, im.T, ucnt);
   if (lane < kTileBlocks) my_stat += ucnt[lane];
   if (lane < tl.count) stat[im.blk_off + tl.first + lane] = my_stat;
+}
+
+// Both phase-1 statistics in one launch, so that the latency-bound BBV
+// threads run beside the DD tiles: workgroups below g_bbv take BBV blocks
+// (one thread per block of the BBV tile list), the rest take DD tiles of
+// 16x16 blocks (one wavefront per tile).
+__global__ __launch_bounds__(kGroupThreads) void k_phase1_stats(const ImgDev* __restrict__ imgs,
+                                                               const Tile* __restrict__ tiles_bbv, int nt_bbv,
+                                                               int g_bbv, const Tile* __restrict__ tiles_dd,
+                                                               int nt_dd, const uint8_t* __restrict__ px,
+                                                               int32_t* __restrict__ stat) {
+  if ((int)blockIdx.x < g_bbv)
+    bbv_stats_thread(imgs, tiles_bbv, nt_bbv, px, stat, blockIdx.x * kGroupThreads + threadIdx.x);
+  else
+    dd_stats_group(imgs, tiles_dd, nt_dd, px, stat, blockIdx.x - g_bbv);
 }
 
 // ---------------------------------------------------------------------------
