@@ -74,9 +74,9 @@ COPY_KIB = 1048576.0
 TRAFFIC = {
     "reconstruct": dict(
         sources=("common.hpp", "transform16.hpp", "sense_kernels.hpp"),
-        sha256="9e0117b2eab08a1ac31a4ebd1a9ade82684d7fe8a6b60b4b36cd9a62997ca8e6",
-        fetch_kib=98088.66, write_kib=655520.47,
-        copy_fetch_kib=524301.24, copy_write_kib=1048576.0),
+        sha256="51758afe2f775adade0753227a1f3780e6c812f137e36b42356328a05466812f",
+        fetch_kib=98092.69, write_kib=655483.94,
+        copy_fetch_kib=524301.31, copy_write_kib=1048576.0),
 }
 
 
@@ -580,6 +580,8 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a device-to-device copy of this many MiB (5 times) and exit; "
                          "its FETCH_SIZE / WRITE_SIZE readings calibrate the traffic counters")
+    ap.add_argument("--bw-probe", type=float, default=0.0,
+                    help="only time a device copy and a fill of this many MiB and print their HBM rates")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the batch would shard by "
@@ -601,6 +603,26 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 5}))
+        return
+    if args.bw_probe > 0:
+        # practical HBM rates of plain torch kernels: a device copy (read +
+        # write) and a fill (write only), 10 timed launches each
+        n = int(args.bw_probe * (1 << 20)) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        out = {"bytes": 4 * n}
+        for name, fn, moved in (("copy", lambda: b.copy_(a), 8 * n), ("fill", lambda: b.fill_(1.5), 4 * n)):
+            for _ in range(3):
+                fn()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            for _ in range(10):
+                fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / 10
+            out[name] = {"ms": round(ms, 4), "GB_per_s": round(moved / ms / 1e6, 1)}
+        print(json.dumps(out))
         return
     log("generating images")
     images = make_images()
