@@ -285,21 +285,37 @@ __global__ __launch_bounds__(256) void k_cnn_last(const ImgDev* __restrict__ img
   const int wave = wave_in_group();
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
   const float b8 = b8p[0];
+  // The next tile's activations (with the one-pixel halo, zero outside the
+  // image) are loaded into registers while the current tile is computed.
+  constexpr int NST = (TH * TW * 8 + 255) / 256;
+  u16x8 pre[NST];
+  auto fetch = [&](int tj) {
+    const CnnTile tn = tiles[tj];
+    const ImgDev imn = imgs[tn.img];
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(act + imn.out_off * kCh, imn.Hc * imn.Wc * kCh * 2);
+#pragma unroll
+    for (int sidx = 0; sidx < NST; ++sidx) {
+      const int t = threadIdx.x + 256 * sidx;
+      const int px = t >> 3, part = t & 7;
+      const int ty = px / TW, tx = px - ty * TW;
+      const int y = tn.y0 + ty - 1, x = tn.x0 + tx - 1;
+      const bool ok = t < TH * TW * 8 && (unsigned)y < (unsigned)imn.Hc && (unsigned)x < (unsigned)imn.Wc;
+      const uint32_t off = ok ? (uint32_t)(((y * imn.Wc + x) * kCh + part * 8) * 2) : 0xffffffffu;
+      pre[sidx] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, off, 0, 0));
+    }
+  };
+  if ((int)blockIdx.x < ntiles) fetch(blockIdx.x);
   for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
     const CnnTile tl = tiles[ti];
     const ImgDev im = imgs[tl.img];
-    const __amdgpu_buffer_rsrc_t ra = make_rsrc(act + im.out_off * kCh, im.Hc * im.Wc * kCh * 2);
     __syncthreads();  // previous tile consumed (and w8s written)
-    for (int t = threadIdx.x; t < TH * TW * 8; t += 256) {
-      const int px = t >> 3, part = t & 7;
-      const int ty = px / TW, tx = px - ty * TW;
-      const int y = tl.y0 + ty - 1, x = tl.x0 + tx - 1;
-      const bool ok = (unsigned)y < (unsigned)im.Hc && (unsigned)x < (unsigned)im.Wc;
-      const uint32_t off = ok ? (uint32_t)(((y * im.Wc + x) * kCh + part * 8) * 2) : 0xffffffffu;
-      *(u16x8*)(tile + px * kPxStride + part * 8) =
-          __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, off, 0, 0));
+#pragma unroll
+    for (int sidx = 0; sidx < NST; ++sidx) {
+      const int t = threadIdx.x + 256 * sidx;
+      if (t < TH * TW * 8) *(u16x8*)(tile + (t >> 3) * kPxStride + (t & 7) * 8) = pre[sidx];
     }
     __syncthreads();
+    if (ti + (int)gridDim.x < ntiles) fetch(ti + gridDim.x);
     f32x4 acc[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) acc[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
