@@ -96,6 +96,7 @@ __device__ __forceinline__ void dd_flush(const uint16_t* list, int n, const uint
   wave_lds_sync();
 }
 
+template <int XF>
 __device__ __forceinline__ void dd_stats_group(const ImgDev* __restrict__ imgs, const Tile* __restrict__ tiles,
                                                int ntiles, const uint8_t* __restrict__ px,
                                                int32_t* __restrict__ stat, int group) {
@@ -103,14 +104,14 @@ __device__ __forceinline__ void dd_stats_group(const ImgDev* __restrict__ imgs, 
   __shared__ PxStage stage[kWavesPerGroup];
   __shared__ uint16_t ulist[kWavesPerGroup][kDDListCap];
   __shared__ int32_t ucount[kWavesPerGroup][kTileBlocks];
-  sD[threadIdx.x] = c_D16d[threadIdx.x];
+  sD[threadIdx.x] = Basis16<XF>::Dd()[threadIdx.x];
   __syncthreads();
   const int wave = group * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
   const Tile tl = tiles[wave];
   const ImgDev im = imgs[tl.img];
   Lane16 L;
-  lane16_init(L);
+  lane16_init<XF>(L);
   Lane16K32 K;
   lane16k32_init(K, L);
   const int lane = threadIdx.x & 63;
@@ -184,7 +185,15 @@ __global__ __launch_bounds__(kGroupThreads) void k_phase1_stats(const ImgDev* __
   if ((int)blockIdx.x < g_bbv)
     bbv_stats_thread(imgs, tiles_bbv, nt_bbv, px, stat, blockIdx.x * kGroupThreads + threadIdx.x);
   else
-    dd_stats_group(imgs, tiles_dd, nt_dd, px, stat, blockIdx.x - g_bbv);
+    dd_stats_group<kXfDCT>(imgs, tiles_dd, nt_dd, px, stat, blockIdx.x - g_bbv);
+}
+
+// DD statistics of 16x16 Walsh-Hadamard tiles (one wavefront per tile).
+__global__ __launch_bounds__(kGroupThreads) void k_dd_stats16_wht(const ImgDev* __restrict__ imgs,
+                                                                 const Tile* __restrict__ tiles, int ntiles,
+                                                                 const uint8_t* __restrict__ px,
+                                                                 int32_t* __restrict__ stat) {
+  dd_stats_group<kXfWHT>(imgs, tiles, ntiles, px, stat, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

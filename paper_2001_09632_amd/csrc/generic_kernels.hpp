@@ -1,5 +1,6 @@
-// Block transforms on the vector ALUs (DCT with B = 8 and B = 32, and the
-// Walsh-Hadamard transform of Section IV with B = 8, 16, 32): phase-1 DD
+// Block transforms on the vector ALUs (DCT and the Walsh-Hadamard transform
+// of Section IV with B = 8 and B = 32; B = 16 runs on the matrix-core kernels
+// for both transforms): phase-1 DD
 // statistic (in float64, in the fixed order of the definition), sensing,
 // masked inverse DCT and the IDA transform step.  A workgroup takes a tile of
 // up to 16 consecutive blocks of a block row; wavefront w handles blocks
@@ -28,17 +29,15 @@ __constant__ uint16_t c_zzpos8[64];
 __constant__ uint16_t c_zzrank32[1024];
 __constant__ uint16_t c_zzpos32[1024];
 // Orthonormal sequency-ordered Walsh-Hadamard bases W[s*B + j] (float32 and
-// float64), and 16-bit zigzag tables for B = 16.
+// float64; the order-16 basis is declared with the 16x16 transforms), and
+// 16-bit zigzag tables for B = 16.
 __constant__ float c_W8[64];
 __constant__ double c_W8d[64];
-__constant__ float c_W16[256];
-__constant__ double c_W16d[256];
 __constant__ float c_W32[1024];
 __constant__ double c_W32d[1024];
 __constant__ uint16_t c_zzrank16w[256];
 __constant__ uint16_t c_zzpos16[256];
 
-constexpr int kXfDCT = 0, kXfWHT = 1;
 
 template <int B, int XF>
 struct GenTables;

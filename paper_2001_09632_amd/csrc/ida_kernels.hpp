@@ -23,6 +23,7 @@ namespace abcs {
 // x^0 = 0 and z^{-1} = 0 are used without reading x or z.  v may alias x.
 // The weight of z^{t-1} is alpha_img[image] when alpha_img is not null
 // (D-AMP's per-image Onsager coefficient), else alpha.
+template <int XF = kXfDCT>
 __global__ __launch_bounds__(kGroupThreads) void k_ida_step16(const ImgDev* __restrict__ imgs,
                                                              const Tile* __restrict__ tiles, int ntiles,
                                                              const float* __restrict__ y,
@@ -38,7 +39,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_ida_step16(const ImgDev* __re
   const ImgDev im = imgs[tl.img];
   if (alpha_img) alpha = alpha_img[tl.img];
   Lane16 L;
-  lane16_init(L);
+  lane16_init<XF>(L);
   TileIO io;
   tile_io_init(io, im, tl, nullptr, y, k_all, off_all, L);
   const __amdgpu_buffer_rsrc_t rz = make_rsrc(z + im.meas_off, (int)(4 * im.n_meas));

@@ -28,7 +28,7 @@ struct WaveLds {
 // an out-of-range offset and are dropped.  Blocks are taken in pairs, so that
 // the matrix cores always have two independent product chains of the wave to
 // work on.
-template <int P>
+template <int P, int XF = kXfDCT>
 __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restrict__ imgs,
                                                           const Tile* __restrict__ tiles, int ntiles,
                                                           const uint8_t* __restrict__ px,
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
   const Tile tl = tiles[wave];
   const ImgDev im = imgs[tl.img];
   Lane16 L;
-  lane16_init(L);
+  lane16_init<XF>(L);
   Lane16P<P> H;
   if (P != kPrecFP32) lane16p_init(H, L);
   TileIO io;
@@ -102,7 +102,7 @@ __device__ __forceinline__ float row_ror8(float v) {
 // Cache policy bits of a buffer store: non-temporal.
 constexpr int kStoreNT = 2;
 
-template <int P>
+template <int P, int XF = kXfDCT>
 __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* __restrict__ imgs,
                                                                 const Tile* __restrict__ tiles, int ntiles,
                                                                 const float* __restrict__ y,
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
   const Tile tl = tiles[wave];
   const ImgDev im = imgs[tl.img];
   Lane16 L;
-  lane16_init(L);
+  lane16_init<XF>(L);
   Lane16P<P> H;
   if (P != kPrecFP32) lane16p_init(H, L);
   TileIO io;

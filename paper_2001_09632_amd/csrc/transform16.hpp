@@ -32,6 +32,20 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 __constant__ float c_D16[256];
 __constant__ double c_D16d[256];
 __constant__ uint8_t c_zzrank16[256];
+// Orthonormal sequency-ordered Walsh-Hadamard basis of order 16, W[s*16 + j]
+// (entries +-1/4, exact in every format used here).
+__constant__ float c_W16[256];
+__constant__ double c_W16d[256];
+
+// Transform of a block: the 2D DCT-II or the 2D Walsh-Hadamard transform.
+// The 16x16 kernels below take either basis; the transform is C = D X D^T in
+// both cases.
+constexpr int kXfDCT = 0, kXfWHT = 1;
+template <int XF>
+struct Basis16 {
+  __device__ static const float* D() { return XF == kXfWHT ? c_W16 : c_D16; }
+  __device__ static const double* Dd() { return XF == kXfWHT ? c_W16d : c_D16d; }
+};
 
 struct Lane16 {
   int g, n;
@@ -40,14 +54,16 @@ struct Lane16 {
   int zr[4];     // zigzag rank of coefficient (4g+c, n)
 };
 
+template <int XF = kXfDCT>
 __device__ __forceinline__ void lane16_init(Lane16& L) {
   const int lane = threadIdx.x & 63;
+  const float* D = Basis16<XF>::D();
   L.g = lane >> 4;
   L.n = lane & 15;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    L.dR[c] = c_D16[L.n * 16 + 4 * L.g + c];
-    L.dT[c] = c_D16[(4 * L.g + c) * 16 + L.n];
+    L.dR[c] = D[L.n * 16 + 4 * L.g + c];
+    L.dT[c] = D[(4 * L.g + c) * 16 + L.n];
     L.zr[c] = c_zzrank16[(4 * L.g + c) * 16 + L.n];
   }
 }
