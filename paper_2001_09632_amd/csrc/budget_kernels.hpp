@@ -403,6 +403,167 @@ __global__ __launch_bounds__(kApThreads) void k_apportion(const ImgDev* __restri
   }
 }
 
+// k_apportion_reg's steps for images of up to kThreads * kPer blocks with
+// 16 bits of state per block in LDS: the weight in bits 0-14 (BBV_i <=
+// 4 n_S 255 <= 16,320 with n_S <= B / 2, and n_i <= m1 <= B^2 / 2, for
+// B <= 32) and bit 15 set once the block is fixed at its cap (and for slots
+// past the image).  Thread t owns blocks [t kPer, t kPer + kPer), stored with
+// a row pitch of kPer + 2 halfwords so that the lanes of a wavefront hit
+// different banks.  The floor share q_i = floor(P w_i / S) and the remainder
+// P w_i - q_i S of a block that is not fixed are recomputed from the final P
+// and S whenever a pass needs them.
+template <int kThreads, int kPer>
+__global__ __launch_bounds__(kThreads) void k_apportion_packed(const ImgDev* __restrict__ imgs,
+                                                               int32_t* __restrict__ stat_all,
+                                                               int32_t* __restrict__ k_all,
+                                                               int64_t* __restrict__ off_all) {
+  constexpr int kWaves = kThreads / 64;
+  constexpr int kPitch = kPer + 2;
+  __shared__ int64_t sh64[kWaves];
+  __shared__ int32_t hist[256];
+  __shared__ int64_t sel_sh[2];
+  __shared__ uint16_t st[kThreads * kPitch];
+  const ImgDev im = imgs[blockIdx.x];
+  const int nB = im.nB;
+  int32_t* wg = stat_all + im.blk_off;
+  int32_t* kg = k_all + im.blk_off;
+  int64_t* og = off_all + im.blk_off;
+  const int tid = threadIdx.x;
+  const int i0 = tid * kPer;
+  uint16_t* my = st + tid * kPitch;
+
+  if (im.mode == kModeZZ) {
+    for (int i = tid; i < nB; i += kThreads) {
+      kg[i] = im.kz;
+      wg[i] = 0;
+      og[i] = im.meas_off + (int64_t)i * im.kz;
+    }
+    return;
+  }
+
+  for (int j = 0; j < kPer; ++j)
+    my[j] = (uint16_t)(i0 + j < nB ? ((uint32_t)wg[i0 + j] & 0x7fffu) : 0x8000u);
+  const int64_t cap = im.cap;
+  int64_t P = im.pool;
+  int64_t S = 0;
+  bool uniform = false;
+  for (;;) {
+    int64_t sw = 0, na = 0;
+#pragma unroll 8
+    for (int j = 0; j < kPer; ++j) {
+      const uint32_t x = my[j];
+      if (x < 0x8000u) {
+        sw += x;
+        na += 1;
+      }
+    }
+    S = group_sum<kWaves>(sw, sh64);
+    const int64_t A = group_sum<kWaves>(na, sh64);
+    if (A == 0) break;
+    uniform = (S == 0);
+    if (uniform) S = A;
+    const int64_t capS = cap * S;
+    int64_t used = 0;
+#pragma unroll 8
+    for (int j = 0; j < kPer; ++j) {
+      const uint32_t x = my[j];
+      if (x < 0x8000u && P * (uniform ? 1 : (int64_t)x) >= capS) {
+        my[j] = (uint16_t)(x | 0x8000u);
+        used += cap;
+      }
+    }
+    used = group_sum<kWaves>(used, sh64);
+    if (used == 0) break;
+    P -= used;
+  }
+  // floor share and remainder of block j (remainder -1 when fixed)
+  auto split = [&](int j, int64_t& q, int64_t& rm) {
+    const uint32_t x = my[j];
+    if (x >= 0x8000u) {
+      q = cap;
+      rm = -1;
+      return;
+    }
+    const int64_t pw = P * (uniform ? 1 : (int64_t)x);
+    q = floor_div_exact(pw, S);
+    rm = pw - q * S;
+  };
+
+  int64_t sq = 0;
+#pragma unroll 4
+  for (int j = 0; j < kPer; ++j) {
+    int64_t q, rm;
+    split(j, q, rm);
+    if (rm >= 0) sq += q;
+  }
+  const int64_t R = P - group_sum<kWaves>(sq, sh64);
+
+  int64_t tau = 0, need = R;
+  if (R > 0 && S > 1) {
+    const int bits = 64 - __clzll((unsigned long long)(S - 1));
+    for (int shift = ((bits + 7) / 8) * 8 - 8; shift >= 0; shift -= 8) {
+      if (tid < 256) hist[tid] = 0;
+      __syncthreads();
+      const uint64_t hi_mask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
+#pragma unroll 4
+      for (int j = 0; j < kPer; ++j) {
+        int64_t q, rm;
+        split(j, q, rm);
+        if (rm >= 0 && ((uint64_t)rm & hi_mask) == ((uint64_t)tau & hi_mask))
+          atomicAdd(&hist[((uint64_t)rm >> shift) & 255u], 1);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        sel_sh[0] = 0;
+        sel_sh[1] = need;
+      }
+      const int32_t bin = tid < 256 ? hist[255 - tid] : 0;
+      const int64_t above_incl = group_exclusive_scan((int64_t)bin, sh64) + bin;
+      if (tid < 256 && above_incl >= need && above_incl - bin < need) {
+        sel_sh[0] = 255 - tid;
+        sel_sh[1] = need - (above_incl - bin);
+      }
+      __syncthreads();
+      tau |= (int64_t)sel_sh[0] << shift;
+      need = sel_sh[1];
+      __syncthreads();
+    }
+  }
+
+  int64_t neq = 0;
+  if (R > 0) {
+#pragma unroll 4
+    for (int j = 0; j < kPer; ++j) {
+      int64_t q, rm;
+      split(j, q, rm);
+      neq += (rm >= 0 && rm == tau) ? 1 : 0;
+    }
+  }
+  int64_t rank = group_exclusive_scan(neq, sh64);
+  const int32_t add = (im.mode == kModeDD) ? im.m1 : 0;
+  int64_t ksum = 0;
+  for (int j = 0; j < kPer && i0 + j < nB; ++j) {
+    int64_t ki, rm;
+    split(j, ki, rm);
+    if (R > 0 && rm >= 0) {
+      if (rm > tau) {
+        ki += 1;
+      } else if (rm == tau) {
+        if (rank < need) ki += 1;
+        rank += 1;
+      }
+    }
+    ki += add;
+    ksum += ki;
+    kg[i0 + j] = (int32_t)ki;
+  }
+  int64_t base = group_exclusive_scan(ksum, sh64) + im.meas_off;
+  for (int j = 0; j < kPer && i0 + j < nB; ++j) {
+    og[i0 + j] = base;
+    base += kg[i0 + j];
+  }
+}
+
 // The same apportionment with each image's blocks held in registers: thread
 // t owns blocks [t kPer, t kPer + kPer), so every pass (the cap loop, the
 // floors, the radix select, the ties and the offsets) works on registers and

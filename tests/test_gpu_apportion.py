@@ -1,0 +1,41 @@
+"""GPU parity of the budget apportionment (eqs 22-23 with the cap rule) on
+each of its kernels, chosen by the plan's largest image: up to 2048 blocks,
+up to 8192 and up to 65,536 blocks (state in registers or LDS), and beyond
+(state in global memory).  Budgets, statistics and offsets bit-exact against
+the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import abcs as orc
+
+from gpu_util import Run, pack_images
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(imgs, reqs):
+    px, d = pack_images(imgs)
+    run = Run(px, [dict(d[s], block=B, subrate=cr, method=m) for s, B, cr, m in reqs]).budget().fetch()
+    for j, (s, B, cr, m) in enumerate(reqs):
+        got = run.image(j)
+        k, stat = orc.budget(imgs[s], B, cr, orc.METHOD_NAMES[m])
+        assert np.array_equal(got["stat"], stat), f"stat (request {j}: {imgs[s].shape}, B {B}, C_R {cr}, {m})"
+        assert np.array_equal(got["k"], k), f"k (request {j}: {imgs[s].shape}, B {B}, C_R {cr}, {m})"
+        assert np.array_equal(got["off"], orc.offsets(k)), f"offsets (request {j})"
+
+
+@pytest.mark.parametrize("size,B", [((1024, 768), 16), ((1024, 1024), 8), ((2048, 2048), 8)])
+def test_apportion_kernels_by_image_size(size, B):
+    """Largest images of 3072, 16,384 and 65,536 blocks (with a small image
+    beside them, so that one plan mixes block counts)."""
+    big = synth.synth_image(4000, *size)
+    small = synth.synth_image(4001, 64, 80)
+    reqs = [(0, B, 0.1, "bbv"), (0, B, 0.35, "dd"), (0, B, 0.5, "bbv"), (1, 16, 0.2, "dd"), (1, 8, 0.3, "zz")]
+    _check([big, small], reqs)
+
+
+def test_apportion_global_memory_kernel():
+    """An image of more than 65,536 blocks (2048 x 2304 at B = 8: 73,728)."""
+    big = synth.synth_image(4002, 2048, 2304)
+    _check([big], [(0, 8, 0.2, "bbv"), (0, 8, 0.45, "dd")])
