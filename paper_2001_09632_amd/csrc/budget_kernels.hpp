@@ -259,6 +259,18 @@ __device__ __forceinline__ int64_t floor_div_exact(int64_t pw, int64_t S) {
   return q;
 }
 
+// The same with a float64 reciprocal of S computed once (rcp_s = 1.0 / S).
+// pw and the quotient are exact in float64 and the quotient (at most the
+// pool, below 2^40) picks up a relative error of about 2^-52 from the two
+// roundings, so the truncated product is within one of floor(pw / S) and the
+// two integer checks settle it.
+__device__ __forceinline__ int64_t floor_div_rcp(int64_t pw, int64_t S, double rcp_s) {
+  int64_t q = (int64_t)((double)pw * rcp_s);
+  if (q * S > pw) q -= 1;
+  if ((q + 1) * S <= pw) q += 1;
+  return q;
+}
+
 template <int kApThreads>
 __global__ __launch_bounds__(kApThreads) void k_apportion(const ImgDev* __restrict__ imgs,
                                                          int32_t* __restrict__ stat_all,
@@ -477,6 +489,7 @@ __global__ __launch_bounds__(kThreads) void k_apportion_packed(const ImgDev* __r
     P -= used;
   }
   // floor share and remainder of block j (remainder -1 when fixed)
+  const double rcp_s = S > 0 ? 1.0 / (double)S : 0.0;
   auto split = [&](int j, int64_t& q, int64_t& rm) {
     const uint32_t x = my[j];
     if (x >= 0x8000u) {
@@ -485,7 +498,7 @@ __global__ __launch_bounds__(kThreads) void k_apportion_packed(const ImgDev* __r
       return;
     }
     const int64_t pw = P * (uniform ? 1 : (int64_t)x);
-    q = floor_div_exact(pw, S);
+    q = floor_div_rcp(pw, S, rcp_s);
     rm = pw - q * S;
   };
 
