@@ -29,14 +29,11 @@ __constant__ uint16_t c_zzpos8[64];
 __constant__ uint16_t c_zzrank32[1024];
 __constant__ uint16_t c_zzpos32[1024];
 // Orthonormal sequency-ordered Walsh-Hadamard bases W[s*B + j] (float32 and
-// float64; the order-16 basis is declared with the 16x16 transforms), and
-// 16-bit zigzag tables for B = 16.
+// float64; the order-16 basis is declared with the 16x16 transforms).
 __constant__ float c_W8[64];
 __constant__ double c_W8d[64];
 __constant__ float c_W32[1024];
 __constant__ double c_W32d[1024];
-__constant__ uint16_t c_zzrank16w[256];
-__constant__ uint16_t c_zzpos16[256];
 
 
 template <int B, int XF>
@@ -61,13 +58,6 @@ struct GenTables<8, kXfWHT> {
   __device__ static const double* Dd() { return c_W8d; }
   __device__ static const uint16_t* rank() { return c_zzrank8; }
   __device__ static const uint16_t* pos() { return c_zzpos8; }
-};
-template <>
-struct GenTables<16, kXfWHT> {
-  __device__ static const float* D() { return c_W16; }
-  __device__ static const double* Dd() { return c_W16d; }
-  __device__ static const uint16_t* rank() { return c_zzrank16w; }
-  __device__ static const uint16_t* pos() { return c_zzpos16; }
 };
 template <>
 struct GenTables<32, kXfWHT> {
