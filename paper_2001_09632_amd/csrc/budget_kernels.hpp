@@ -259,18 +259,6 @@ __device__ __forceinline__ int64_t floor_div_exact(int64_t pw, int64_t S) {
   return q;
 }
 
-// The same with a float64 reciprocal of S computed once (rcp_s = 1.0 / S).
-// pw and the quotient are exact in float64 and the quotient (at most the
-// pool, below 2^40) picks up a relative error of about 2^-52 from the two
-// roundings, so the truncated product is within one of floor(pw / S) and the
-// two integer checks settle it.
-__device__ __forceinline__ int64_t floor_div_rcp(int64_t pw, int64_t S, double rcp_s) {
-  int64_t q = (int64_t)((double)pw * rcp_s);
-  if (q * S > pw) q -= 1;
-  if ((q + 1) * S <= pw) q += 1;
-  return q;
-}
-
 template <int kApThreads>
 __global__ __launch_bounds__(kApThreads) void k_apportion(const ImgDev* __restrict__ imgs,
                                                          int32_t* __restrict__ stat_all,
@@ -415,34 +403,36 @@ __global__ __launch_bounds__(kApThreads) void k_apportion(const ImgDev* __restri
   }
 }
 
-// k_apportion_reg's steps for images of up to kThreads * kPer blocks with
-// 16 bits of state per block in LDS: the weight in bits 0-14 (BBV_i <=
-// 4 n_S 255 <= 16,320 with n_S <= B / 2, and n_i <= m1 <= B^2 / 2, for
-// B <= 32) and bit 15 set once the block is fixed at its cap (and for slots
-// past the image).  Thread t owns blocks [t kPer, t kPer + kPer), stored with
-// a row pitch of kPer + 2 halfwords so that the lanes of a wavefront hit
-// different banks.  The floor share q_i = floor(P w_i / S) and the remainder
-// P w_i - q_i S of a block that is not fixed are recomputed from the final P
-// and S whenever a pass needs them.
-template <int kThreads, int kPer>
-__global__ __launch_bounds__(kThreads) void k_apportion_packed(const ImgDev* __restrict__ imgs,
-                                                               int32_t* __restrict__ stat_all,
-                                                               int32_t* __restrict__ k_all,
-                                                               int64_t* __restrict__ off_all) {
-  constexpr int kWaves = kThreads / 64;
-  constexpr int kPitch = kPer + 2;
+// The apportionment over a histogram of the weights, for images of more than
+// 8192 blocks.  Every step of k_apportion_reg depends on a block only through
+// its weight, except the tie order among equal remainders, so the cap loop,
+// the floors and the radix select run on the counts H[w] of blocks per weight
+// (kApBins bins; BBV_i <= 4 n_S 255 <= 16,320 with n_S <= B / 2, and
+// n_i <= m1 <= B^2 / 2, for B <= 32): the blocks fixed at the cap in one
+// round are those with P w >= cap S, i.e. every open weight from
+// ceil(cap S / P) up, so the open blocks are always the weights below a
+// threshold.  Two passes over the blocks in index order then give the tie
+// ranks and the final shares and offsets.  Remainders are kept in int32,
+// which holds S for images of up to kApHistMaxBlocks blocks.
+constexpr int kApBins = 16384;
+constexpr int kApHistMaxBlocks = 131072;
+
+__global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restrict__ imgs,
+                                                        int32_t* __restrict__ stat_all,
+                                                        int32_t* __restrict__ k_all,
+                                                        int64_t* __restrict__ off_all) {
+  constexpr int kThreads = 1024, kWaves = kThreads / 64, kPerBin = kApBins / kThreads;
   __shared__ int64_t sh64[kWaves];
   __shared__ int32_t hist[256];
   __shared__ int64_t sel_sh[2];
-  __shared__ uint16_t st[kThreads * kPitch];
+  __shared__ int32_t H[kApBins];    // blocks per weight
+  __shared__ int32_t REM[kApBins];  // remainder of an open weight, -1 otherwise
   const ImgDev im = imgs[blockIdx.x];
   const int nB = im.nB;
   int32_t* wg = stat_all + im.blk_off;
   int32_t* kg = k_all + im.blk_off;
   int64_t* og = off_all + im.blk_off;
   const int tid = threadIdx.x;
-  const int i0 = tid * kPer;
-  uint16_t* my = st + tid * kPitch;
 
   if (im.mode == kModeZZ) {
     for (int i = tid; i < nB; i += kThreads) {
@@ -453,61 +443,57 @@ __global__ __launch_bounds__(kThreads) void k_apportion_packed(const ImgDev* __r
     return;
   }
 
-  for (int j = 0; j < kPer; ++j)
-    my[j] = (uint16_t)(i0 + j < nB ? ((uint32_t)wg[i0 + j] & 0x7fffu) : 0x8000u);
+  for (int b = tid; b < kApBins; b += kThreads) H[b] = 0;
+  __syncthreads();
+  for (int i = tid; i < nB; i += kThreads) atomicAdd(&H[wg[i] & (kApBins - 1)], 1);
+  __syncthreads();
+
   const int64_t cap = im.cap;
   int64_t P = im.pool;
   int64_t S = 0;
   bool uniform = false;
+  int wcap = kApBins;  // open weights are those below wcap
   for (;;) {
     int64_t sw = 0, na = 0;
-#pragma unroll 8
-    for (int j = 0; j < kPer; ++j) {
-      const uint32_t x = my[j];
-      if (x < 0x8000u) {
-        sw += x;
-        na += 1;
-      }
+    for (int b = tid; b < wcap; b += kThreads) {
+      sw += (int64_t)H[b] * b;
+      na += H[b];
     }
     S = group_sum<kWaves>(sw, sh64);
     const int64_t A = group_sum<kWaves>(na, sh64);
     if (A == 0) break;
     uniform = (S == 0);
-    if (uniform) S = A;
-    const int64_t capS = cap * S;
-    int64_t used = 0;
-#pragma unroll 8
-    for (int j = 0; j < kPer; ++j) {
-      const uint32_t x = my[j];
-      if (x < 0x8000u && P * (uniform ? 1 : (int64_t)x) >= capS) {
-        my[j] = (uint16_t)(x | 0x8000u);
-        used += cap;
+    if (uniform) {
+      // every open block has weight 0 and counts as weight 1
+      S = A;
+      if (P >= cap * S) {
+        P -= cap * A;
+        wcap = 0;
       }
+      break;
     }
-    used = group_sum<kWaves>(used, sh64);
-    if (used == 0) break;
-    P -= used;
+    if (P <= 0) break;
+    const int64_t wstar = (cap * S + P - 1) / P;  // smallest w with P w >= cap S
+    if (wstar >= wcap) break;
+    int64_t nc = 0;
+    for (int b = (int)wstar + tid; b < wcap; b += kThreads) nc += H[b];
+    nc = group_sum<kWaves>(nc, sh64);
+    if (nc == 0) break;
+    wcap = (int)wstar;
+    P -= cap * nc;
   }
-  // floor share and remainder of block j (remainder -1 when fixed)
-  const double rcp_s = S > 0 ? 1.0 / (double)S : 0.0;
-  auto split = [&](int j, int64_t& q, int64_t& rm) {
-    const uint32_t x = my[j];
-    if (x >= 0x8000u) {
-      q = cap;
-      rm = -1;
-      return;
-    }
-    const int64_t pw = P * (uniform ? 1 : (int64_t)x);
-    q = floor_div_rcp(pw, S, rcp_s);
-    rm = pw - q * S;
-  };
 
+  // floors and remainders per open weight
   int64_t sq = 0;
-#pragma unroll 4
-  for (int j = 0; j < kPer; ++j) {
-    int64_t q, rm;
-    split(j, q, rm);
-    if (rm >= 0) sq += q;
+  for (int b = tid; b < kApBins; b += kThreads) {
+    int32_t rm = -1;
+    if (b < wcap && H[b] > 0) {
+      const int64_t pw = P * (uniform ? 1 : (int64_t)b);
+      const int64_t q = floor_div_exact(pw, S);
+      rm = (int32_t)(pw - q * S);
+      sq += H[b] * q;
+    }
+    REM[b] = rm;
   }
   const int64_t R = P - group_sum<kWaves>(sq, sh64);
 
@@ -518,12 +504,12 @@ __global__ __launch_bounds__(kThreads) void k_apportion_packed(const ImgDev* __r
       if (tid < 256) hist[tid] = 0;
       __syncthreads();
       const uint64_t hi_mask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
-#pragma unroll 4
-      for (int j = 0; j < kPer; ++j) {
-        int64_t q, rm;
-        split(j, q, rm);
+#pragma unroll
+      for (int j = 0; j < kPerBin; ++j) {
+        const int b = tid + kThreads * j;
+        const int64_t rm = REM[b];
         if (rm >= 0 && ((uint64_t)rm & hi_mask) == ((uint64_t)tau & hi_mask))
-          atomicAdd(&hist[((uint64_t)rm >> shift) & 255u], 1);
+          atomicAdd(&hist[((uint64_t)rm >> shift) & 255u], H[b]);
       }
       __syncthreads();
       if (tid == 0) {
@@ -543,37 +529,58 @@ __global__ __launch_bounds__(kThreads) void k_apportion_packed(const ImgDev* __r
     }
   }
 
+  // Blocks in index order, coalesced: wavefront v owns the range
+  // [v span, v span + span) and walks it 64 blocks at a time, lane l taking
+  // block base + l, so that ranks among equal remainders and the offsets
+  // follow the index order through ballots and in-wave scans.
+  const int lane = tid & 63, wave = tid >> 6;
+  const int span = (((nB + kWaves - 1) / kWaves) + 63) & ~63;
+  const int v0 = min(nB, wave * span), v1 = min(nB, v0 + span);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes under this one
   int64_t neq = 0;
-  if (R > 0) {
-#pragma unroll 4
-    for (int j = 0; j < kPer; ++j) {
-      int64_t q, rm;
-      split(j, q, rm);
-      neq += (rm >= 0 && rm == tau) ? 1 : 0;
+  if (R > 0)
+    for (int base = v0; base < v1; base += 64) {
+      const int i = base + lane;
+      const int32_t rm = i < v1 ? REM[wg[i] & (kApBins - 1)] : -1;
+      neq += __popcll(__ballot(rm >= 0 && rm == tau));
     }
-  }
-  int64_t rank = group_exclusive_scan(neq, sh64);
+  // ranks: wavefronts in order (lane 0 of each holds the wave's count)
+  int64_t rank = group_exclusive_scan(lane == 0 ? neq : (int64_t)0, sh64);
+  rank = __shfl(rank, 0, 64);
   const int32_t add = (im.mode == kModeDD) ? im.m1 : 0;
   int64_t ksum = 0;
-  for (int j = 0; j < kPer && i0 + j < nB; ++j) {
-    int64_t ki, rm;
-    split(j, ki, rm);
-    if (R > 0 && rm >= 0) {
-      if (rm > tau) {
-        ki += 1;
-      } else if (rm == tau) {
-        if (rank < need) ki += 1;
-        rank += 1;
+  for (int base = v0; base < v1; base += 64) {
+    const int i = base + lane;
+    const bool valid = i < v1;
+    const int w = valid ? (wg[i] & (kApBins - 1)) : 0;
+    const int32_t rm = valid ? REM[w] : -1;
+    const uint64_t eq = __ballot(R > 0 && rm >= 0 && rm == tau);
+    int64_t ki = cap;
+    if (rm >= 0) {
+      ki = floor_div_exact(P * (uniform ? 1 : (int64_t)w), S);
+      if (R > 0) {
+        if (rm > tau) ki += 1;
+        else if (rm == tau && rank + __popcll(eq & below) < need) ki += 1;
       }
     }
     ki += add;
-    ksum += ki;
-    kg[i0 + j] = (int32_t)ki;
+    if (valid) kg[i] = (int32_t)ki;
+    rank += __popcll(eq);
+    ksum += wave_sum_t<int64_t>(valid ? ki : 0);
   }
-  int64_t base = group_exclusive_scan(ksum, sh64) + im.meas_off;
-  for (int j = 0; j < kPer && i0 + j < nB; ++j) {
-    og[i0 + j] = base;
-    base += kg[i0 + j];
+  int64_t obase = group_exclusive_scan(lane == 0 ? ksum : (int64_t)0, sh64);
+  obase = __shfl(obase, 0, 64) + im.meas_off;
+  for (int base = v0; base < v1; base += 64) {
+    const int i = base + lane;
+    const int32_t kv = i < v1 ? kg[i] : 0;
+    int32_t inc = kv;  // inclusive scan over the 64 lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t u = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += u;
+    }
+    if (i < v1) og[i] = obase + inc - kv;
+    obase += __shfl(inc, 63, 64);
   }
 }
 

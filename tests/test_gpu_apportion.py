@@ -1,8 +1,8 @@
 """GPU parity of the budget apportionment (eqs 22-23 with the cap rule) on
-each of its kernels, chosen by the plan's largest image: up to 2048 blocks,
-up to 8192 and up to 65,536 blocks (state in registers or LDS), and beyond
-(state in global memory).  Budgets, statistics and offsets bit-exact against
-the FP64 oracle."""
+each of its kernels, chosen by the plan's largest image: up to 2048 and up
+to 8192 blocks (blocks in registers), up to 131,072 blocks (on a histogram
+of the weights) and beyond (blocks in global memory).  Budgets, statistics
+and offsets bit-exact against the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -27,15 +27,22 @@ def _check(imgs, reqs):
 
 @pytest.mark.parametrize("size,B", [((1024, 768), 16), ((1024, 1024), 8), ((2048, 2048), 8)])
 def test_apportion_kernels_by_image_size(size, B):
-    """Largest images of 3072, 16,384 and 65,536 blocks (with a small image
-    beside them, so that one plan mixes block counts)."""
+    """Largest images of 3072 (registers), 16,384 and 65,536 blocks
+    (histogram), with a small image beside them, so that one plan mixes block
+    counts."""
     big = synth.synth_image(4000, *size)
     small = synth.synth_image(4001, 64, 80)
     reqs = [(0, B, 0.1, "bbv"), (0, B, 0.35, "dd"), (0, B, 0.5, "bbv"), (1, 16, 0.2, "dd"), (1, 8, 0.3, "zz")]
     _check([big, small], reqs)
 
 
-def test_apportion_global_memory_kernel():
-    """An image of more than 65,536 blocks (2048 x 2304 at B = 8: 73,728)."""
+def test_apportion_histogram_kernel_many_weights():
+    """73,728 blocks (2048 x 2304 at B = 8), BBV weights spread widely."""
     big = synth.synth_image(4002, 2048, 2304)
     _check([big], [(0, 8, 0.2, "bbv"), (0, 8, 0.45, "dd")])
+
+
+def test_apportion_global_memory_kernel():
+    """An image of more than 131,072 blocks (2048 x 4608 at B = 8: 147,456)."""
+    big = synth.synth_image(4003, 2048, 4608)
+    _check([big], [(0, 8, 0.3, "bbv"), (0, 8, 0.25, "dd")])
