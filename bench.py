@@ -74,9 +74,9 @@ COPY_KIB = 1048576.0
 TRAFFIC = {
     "reconstruct": dict(
         sources=("common.hpp", "transform16.hpp", "sense_kernels.hpp"),
-        sha256="51758afe2f775adade0753227a1f3780e6c812f137e36b42356328a05466812f",
-        fetch_kib=98092.69, write_kib=655483.94,
-        copy_fetch_kib=524301.31, copy_write_kib=1048576.0),
+        sha256="133229ccb0b17bf56307791c43d5603572a737ec02b3ea94f532746f106f11c0",
+        fetch_kib=98084.91, write_kib=655510.03,
+        copy_fetch_kib=524301.21, copy_write_kib=1048576.0),
 }
 
 
