@@ -559,22 +559,27 @@ __global__ __launch_bounds__(256) void k_cnn_mid_wgrad(const ImgDev* __restrict_
   for (int cg = 0; cg < 4; ++cg)
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) acc[cg][tap] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  float bacc = 0.f;  // thread t < 64: bias gradient of channel t
+  float bacc = 0.f;  // threads 4c: bias gradient of channel c
   for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
     const CnnTile tl = tiles[ti];
     const ImgDev im = imgs[tl.img];
     __syncthreads();
-    // dz tile -> dzT[co][row * 16 + col]
+    // dz tile -> dzT[co][row * 16 + col].  Item t is pixel t % NPX, channels
+    // 8 (t / NPX) .. + 7: the lanes of a wavefront take consecutive pixels of
+    // one channel group, so that their transposed 16-bit writes land in
+    // different LDS banks.
     for (int t = threadIdx.x; t < NPX * 8; t += 256) {
-      const int px = t >> 3, part8 = t & 7;
+      const int px = t % NPX, part8 = t / NPX;
       const int y = tl.y0 + px / kTileW, x = tl.x0 + px % kTileW;
       const u16x8 val = *(const u16x8*)(dz + (im.out_off + (int64_t)y * im.Wc + x) * kCh + part8 * 8);
 #pragma unroll
       for (int k = 0; k < 8; ++k) dzT[(part8 * 8 + k) * NPX + px] = val[k];
     }
     // a tile with halo -> aT[dx][ci][row][col] = a[y0 - 1 + row][x0 - 1 + dx + col][ci]
-    for (int t = threadIdx.x; t < (kTileH + 2) * (kTileW + 2) * 8; t += 256) {
-      const int px = t >> 3, part8 = t & 7;
+    // (item t: halo pixel t % 180, channels 8 (t / 180) .. + 7, as above)
+    constexpr int NHALO = (kTileH + 2) * (kTileW + 2);
+    for (int t = threadIdx.x; t < NHALO * 8; t += 256) {
+      const int px = t % NHALO, part8 = t / NHALO;
       const int row = px / (kTileW + 2), col = px % (kTileW + 2);
       const int y = tl.y0 - 1 + row, x = tl.x0 - 1 + col;
       u16x8 val = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -591,8 +596,17 @@ __global__ __launch_bounds__(256) void k_cnn_mid_wgrad(const ImgDev* __restrict_
       }
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
-      for (int px = 0; px < NPX; ++px) bacc += bf2f(dzT[threadIdx.x * NPX + px]);
+    {
+      // bias gradient: thread t sums channel t / 4 over pixels 32 (t % 4) ..
+      // + 31, starting at a channel-dependent rotation so that the lanes of a
+      // wavefront read different banks; lanes t .. t + 3 then combine.
+      const int c = threadIdx.x >> 2, q = threadIdx.x & 3;
+      float s4 = 0.f;
+#pragma unroll 8
+      for (int i = 0; i < 32; ++i) s4 += bf2f(dzT[c * NPX + 32 * q + ((i + 2 * c) & 31)]);
+      s4 += __shfl_xor(s4, 1, 64);
+      s4 += __shfl_xor(s4, 2, 64);
+      bacc += s4;  // lanes with q == 0 keep the channel's sum
     }
     // K = 128 pixels in 4 chunks of 32 (2 rows x 16 cols); lane group g
     // covers row 2 kc + g / 2, columns 8 (g % 2) .. + 8.
@@ -621,7 +635,7 @@ __global__ __launch_bounds__(256) void k_cnn_mid_wgrad(const ImgDev* __restrict_
     for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
       for (int r = 0; r < 4; ++r) out[((16 * cg + 4 * g + r) * 9 + tap) * 64 + 16 * wave + n] = acc[cg][tap][r];
-  if (threadIdx.x < 64) out[kMidW + threadIdx.x] = bacc;
+  if ((threadIdx.x & 3) == 0) out[kMidW + (threadIdx.x >> 2)] = bacc;
 }
 
 // out[i] = sum over w < nparts of part[w * stride + i] (fixed order).
