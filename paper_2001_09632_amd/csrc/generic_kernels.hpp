@@ -375,4 +375,224 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_ida_step(const ImgDev* __
   }
 }
 
+// ---------------------------------------------------------------------------
+// B = 32 on the float32 matrix cores.  A 32x32 block is a 2x2 arrangement of
+// 16x16 sub-blocks, X_ik = rows 16i.., columns 16k.., and likewise D_ab for
+// the basis, so the separable transform becomes products of 16x16 tiles on
+// v_mfma_f32_16x16x4f32 with the K mapping of the 16x16 kernels (lane
+// l = 16g + n; a stage's accumulators are the next stage's B operand):
+//   forward  T_ij = sum_k X_ik D_jk^T,        C_ij = sum_k D_ik T_kj
+//   inverse  Q_ij = sum_k C_ki^T D_kj,   (X^T)_ij = sum_k D_ki^T Q_kj
+// 32 products per stage (64 per block), one wavefront per tile of up to 16
+// blocks, taken one after the other.  Lane (g, n) keeps the basis tiles in
+// both operand layouts: dR[a][b][c] = D[16a + n][16b + 4g + c] and
+// dT[a][b][c] = D[16a + 4g + c][16b + n].
+// ---------------------------------------------------------------------------
+struct Lane32 {
+  int g, n;
+  float dR[2][2][4], dT[2][2][4];
+};
+
+template <int XF>
+__device__ __forceinline__ void lane32_init(Lane32& L) {
+  const float* D = GenTables<32, XF>::D();
+  const int lane = threadIdx.x & 63;
+  L.g = lane >> 4;
+  L.n = lane & 15;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        L.dR[a][b][c] = D[(16 * a + L.n) * 32 + 16 * b + 4 * L.g + c];
+        L.dT[a][b][c] = D[(16 * a + 4 * L.g + c) * 32 + 16 * b + L.n];
+      }
+}
+
+// x[i][k][c] = X[16i + n][16k + 4g + c]  ->  C[i][j][r] = C[16i + 4g + r][16j + n]
+__device__ __forceinline__ void dct32_fwd(const float x[2][2][4], const Lane32& L, f32x4 C[2][2]) {
+  f32x4 T[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      f32x4 t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) t = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][k][c], L.dR[j][k][c], t, 0, 0, 0);
+      T[i][j] = t;
+    }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      f32x4 o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o = __builtin_amdgcn_mfma_f32_16x16x4f32(L.dR[i][k][c], T[k][j][c], o, 0, 0, 0);
+      C[i][j] = o;
+    }
+}
+
+// e[k][i][c] = C[16k + 4g + c][16i + n]  ->  X[i][j][r] = X[16j + n][16i + 4g + r]
+__device__ __forceinline__ void idct32_inv(const float e[2][2][4], const Lane32& L, f32x4 X[2][2]) {
+  f32x4 Q[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      f32x4 q = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) q = __builtin_amdgcn_mfma_f32_16x16x4f32(e[k][i][c], L.dT[k][j][c], q, 0, 0, 0);
+      Q[i][j] = q;
+    }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      f32x4 o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o = __builtin_amdgcn_mfma_f32_16x16x4f32(L.dT[k][i][c], Q[k][j][c], o, 0, 0, 0);
+      X[i][j] = o;
+    }
+}
+
+struct WaveLds32 {
+  float c[1024];
+};
+
+// y[off_i + z] = C_i[zigzag[z]] for z < k_i (B = 32): the block's
+// coefficients go to LDS at their zigzag rank, then leave in unit-stride
+// stores of k_i values.
+template <int XF>
+__global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restrict__ imgs,
+                                                          const Tile* __restrict__ tiles, int ntiles,
+                                                          const uint8_t* __restrict__ px,
+                                                          const int32_t* __restrict__ k_all,
+                                                          const int64_t* __restrict__ off_all,
+                                                          float* __restrict__ y) {
+  __shared__ WaveLds32 lds[kWavesPerGroup];
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= ntiles) return;
+  const Tile tl = tiles[wave];
+  const ImgDev im = imgs[tl.img];
+  Lane32 L;
+  lane32_init<XF>(L);
+  const int lane = threadIdx.x & 63;
+  int zr[2][2][4];  // zigzag rank of coefficient (16i + 4g + r, 16j + n)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zr[i][j][r] = c_zzrank32[(16 * i + 4 * L.g + r) * 32 + 16 * j + L.n];
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, 31 * im.pitch + 32 * tl.count);
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(y + im.meas_off, (int)(4 * im.n_meas));
+  const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(off_all + im.blk_off + tl.first, 8 * tl.count);
+  const int32_t kl = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rk, 4 * lane, 0, 0);
+  const int32_t rl = (int32_t)(__builtin_amdgcn_raw_buffer_load_b32(ro, 8 * lane, 0, 0) - (uint32_t)im.meas_off);
+  float* buf = lds[wave_in_group()].c;
+  for (int b = 0; b < tl.count; ++b) {
+    float x[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const uint32_t w =
+            __builtin_amdgcn_raw_buffer_load_b32(rp, (16 * i + L.n) * im.pitch + 32 * b + 16 * k + 4 * L.g, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[i][k][c] = (float)((w >> (8 * c)) & 0xffu);
+      }
+    f32x4 C[2][2];
+    dct32_fwd(x, L, C);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) buf[zr[i][j][r]] = C[i][j][r];
+    wave_lds_sync();
+    const int kk = __builtin_amdgcn_readlane(kl, b);
+    const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(rl, b);
+    for (int q = 0; q < 16 && 64 * q < kk; ++q) {
+      const int z = lane + 64 * q;
+      const uint32_t voff = z < kk ? rel4 + 4u * (uint32_t)z : 0xffffffffu;
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(buf[z]), ry, voff, 0, 0);
+    }
+    wave_lds_sync();
+  }
+}
+
+// out = D^T C D per block (B = 32), C zero beyond the block's k_i zigzag
+// entries: the block's coefficients are staged in LDS in zigzag order (zero
+// past k_i) and gathered in the inverse's operand layout.
+template <int XF>
+__global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* __restrict__ imgs,
+                                                                const Tile* __restrict__ tiles, int ntiles,
+                                                                const float* __restrict__ y,
+                                                                const int32_t* __restrict__ k_all,
+                                                                const int64_t* __restrict__ off_all,
+                                                                float* __restrict__ out) {
+  typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+  __shared__ WaveLds32 lds[kWavesPerGroup];
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= ntiles) return;
+  const Tile tl = tiles[wave];
+  const ImgDev im = imgs[tl.img];
+  Lane32 L;
+  lane32_init<XF>(L);
+  const int lane = threadIdx.x & 63;
+  int zr[2][2][4];  // zigzag rank of coefficient (16k + 4g + c, 16i + n)
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) zr[k][i][c] = c_zzrank32[(16 * k + 4 * L.g + c) * 32 + 16 * i + L.n];
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(y + im.meas_off, (int)(4 * im.n_meas));
+  const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(off_all + im.blk_off + tl.first, 8 * tl.count);
+  const __amdgpu_buffer_rsrc_t rout = make_rsrc(out + tl.out_base, 4 * (31 * im.Wc + 32 * tl.count));
+  const int32_t kl = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rk, 4 * lane, 0, 0);
+  const int32_t rl = (int32_t)(__builtin_amdgcn_raw_buffer_load_b32(ro, 8 * lane, 0, 0) - (uint32_t)im.meas_off);
+  float* buf = lds[wave_in_group()].c;
+  for (int b = 0; b < tl.count; ++b) {
+    const int kk = __builtin_amdgcn_readlane(kl, b);
+    const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(rl, b);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int z = lane + 64 * q;
+      const uint32_t voff = z < kk ? rel4 + 4u * (uint32_t)z : 0xffffffffu;
+      buf[z] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ry, voff, 0, 0));
+    }
+    wave_lds_sync();
+    float e[2][2][4];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) e[k][i][c] = buf[zr[k][i][c]];
+    wave_lds_sync();
+    f32x4 X[2][2];
+    idct32_inv(e, L, X);
+    // X[i][j][r] = pixel (16j + n, 16i + 4g + r)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const uint32_t off = 4u * (uint32_t)((16 * j + L.n) * im.Wc + 32 * b + 16 * i + 4 * L.g);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X[i][j]), rout, off, 0, kStoreNT);
+      }
+  }
+}
+
 }  // namespace abcs
