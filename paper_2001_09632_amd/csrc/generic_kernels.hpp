@@ -1,14 +1,14 @@
-// Block transforms on the vector ALUs (DCT and the Walsh-Hadamard transform
-// of Section IV with B = 8 and B = 32; B = 16 runs on the matrix-core kernels
-// for both transforms): phase-1 DD
-// statistic (in float64, in the fixed order of the definition), sensing,
-// masked inverse DCT and the IDA transform step.  A workgroup takes a tile of
-// up to 16 consecutive blocks of a block row; wavefront w handles blocks
-// w, w + 4, ... of it.  Each wavefront keeps its block in LDS (row pitch B + 1
-// floats, so that a row and a column are both conflict-free) and runs the
-// separable transform as two passes of B-term dot products, one output per
-// lane per step.  The basis and the zigzag rank table are staged in LDS once
-// per workgroup.
+// Block transforms of B = 8 and B = 32 (DCT and the Walsh-Hadamard transform
+// of Section IV).  On the vector ALUs: the phase-1 DD statistic (in float64,
+// in the fixed order of the definition) and the IDA transform step.  A
+// workgroup takes a tile of up to 16 consecutive blocks of a block row;
+// wavefront w handles blocks w, w + 4, ... of it.  Each wavefront keeps its
+// block in LDS (row pitch B + 1 floats, so that a row and a column are both
+// conflict-free) and runs the separable transform as two passes of B-term dot
+// products, one output per lane per step.  The basis and the zigzag rank
+// table are staged in LDS once per workgroup.  Sensing and the inverse
+// transform of both block sizes run on the float32 matrix cores (k_sense32 /
+// k_reconstruct32 and k_sense8 / k_reconstruct8 at the end of this file).
 #pragma once
 
 #include "common.hpp"
@@ -225,84 +225,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_dd_stats(const ImgDev* __
     }
     cnt = wave_sum_i32(cnt);
     if (lane == 0) stat[im.blk_off + tl.first + bb] = cnt;
-    wave_lds_sync();
-  }
-}
-
-// y[off_i + z] = C_i[zigzag(z)] for z < k_i.
-template <int B, int XF>
-__global__ __launch_bounds__(kGroupThreads) void k_gen_sense(const ImgDev* __restrict__ imgs,
-                                                            const Tile* __restrict__ tiles, int ntiles,
-                                                            const uint8_t* __restrict__ px,
-                                                            const int32_t* __restrict__ k_all,
-                                                            const int64_t* __restrict__ off_all,
-                                                            float* __restrict__ y) {
-  constexpr int P = B + 1;
-  __shared__ GenShared<B> sh;
-  if ((int)blockIdx.x >= ntiles) return;
-  gen_load_tables<B, XF>(sh);
-  __syncthreads();
-  const Tile tl = tiles[blockIdx.x];
-  const ImgDev im = imgs[tl.img];
-  const int w = wave_in_group(), lane = threadIdx.x & 63;
-  const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, (B - 1) * im.pitch + B * tl.count);
-  float* a = sh.a[w];
-  float* b = sh.b[w];
-  float* ym = y + im.meas_off;
-  for (int bb = w; bb < tl.count; bb += kWavesPerGroup) {
-    gen_load_pixels<B>(rp, im.pitch, bb, a);
-    wave_lds_sync();
-    gen_fwd<B>(sh.D, a, b);
-    // rank-ordered copy in b (as a flat array of B*B)
-    for (int idx = lane; idx < B * B; idx += 64) {
-      const int u = idx / B, v = idx - u * B;
-      b[sh.rank[idx]] = a[u * P + v];
-    }
-    wave_lds_sync();
-    int kk;
-    int64_t rel;
-    gen_block_range(im, k_all, off_all, im.blk_off + tl.first + bb, B * B, kk, rel);
-    for (int z = lane; z < kk; z += 64) ym[rel + z] = b[z];
-    wave_lds_sync();
-  }
-}
-
-// out = D^T C D per block, C zero beyond the block's k_i zigzag entries.
-template <int B, int XF>
-__global__ __launch_bounds__(kGroupThreads) void k_gen_reconstruct(const ImgDev* __restrict__ imgs,
-                                                                  const Tile* __restrict__ tiles, int ntiles,
-                                                                  const float* __restrict__ y,
-                                                                  const int32_t* __restrict__ k_all,
-                                                                  const int64_t* __restrict__ off_all,
-                                                                  float* __restrict__ out) {
-  constexpr int P = B + 1;
-  __shared__ GenShared<B> sh;
-  if ((int)blockIdx.x >= ntiles) return;
-  gen_load_tables<B, XF>(sh);
-  __syncthreads();
-  const Tile tl = tiles[blockIdx.x];
-  const ImgDev im = imgs[tl.img];
-  const int w = wave_in_group(), lane = threadIdx.x & 63;
-  float* a = sh.a[w];
-  float* b = sh.b[w];
-  const float* ym = y + im.meas_off;
-  for (int bb = w; bb < tl.count; bb += kWavesPerGroup) {
-    int kk;
-    int64_t rel;
-    gen_block_range(im, k_all, off_all, im.blk_off + tl.first + bb, B * B, kk, rel);
-    for (int z = lane; z < B * B; z += 64) b[z] = z < kk ? ym[rel + z] : 0.f;
-    wave_lds_sync();
-    for (int idx = lane; idx < B * B; idx += 64) {
-      const int u = idx / B, v = idx - u * B;
-      a[u * P + v] = b[sh.rank[idx]];
-    }
-    wave_lds_sync();
-    gen_inv<B>(sh.D, a, b);
-    float* o = out + tl.out_base + B * bb;
-    for (int idx = lane; idx < B * B; idx += 64) {
-      const int x = idx / B, xp = idx - x * B;
-      o[(int64_t)x * im.Wc + xp] = a[x * P + xp];
-    }
     wave_lds_sync();
   }
 }
@@ -592,6 +514,143 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* _
         const uint32_t off = 4u * (uint32_t)((16 * j + L.n) * im.Wc + 32 * b + 16 * i + 4 * L.g);
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X[i][j]), rout, off, 0, kStoreNT);
       }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// B = 8 on the float32 matrix cores.  Four consecutive blocks b0 .. b0 + 3 of
+// a tile are placed as the quadrants of a 16x16 array (block b0 + 2p + q at
+// rows 8p .., columns 8q ..) and transformed with the block-diagonal basis
+// diag(D8, D8): its zero off-diagonal blocks keep the quadrants apart, so the
+// 16x16 transform of the 16x16 kernels (eight v_mfma_f32_16x16x4f32) yields
+// the four 8x8 transforms at once.
+//   lane (g, n) operand x[c] = X16[n][4g + c]: block b0 + 2 (n / 8) + g / 2,
+//     pixel row n % 8, columns 4 (g % 2) + c;
+//   forward output C16[4g + r][n]: block b0 + 2 (g / 2) + n / 8, coefficient
+//     (4 (g % 2) + r, n % 8);
+//   inverse operand e[c] = C16[4g + c][n] (same block and coefficient as the
+//   forward output), output X16[n][4g + r] (same block and pixels as x).
+// ---------------------------------------------------------------------------
+template <int XF>
+__device__ __forceinline__ void lane8x4_init(Lane16& L) {
+  const float* D = GenTables<8, XF>::D();
+  const int lane = threadIdx.x & 63;
+  L.g = lane >> 4;
+  L.n = lane & 15;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int j = 4 * L.g + c;  // 0..15
+    // diag(D8, D8)[u][j] = D8[u % 8][j % 8] when u / 8 == j / 8, else 0
+    L.dR[c] = (L.n >> 3) == (j >> 3) ? D[(L.n & 7) * 8 + (j & 7)] : 0.f;
+    L.dT[c] = (j >> 3) == (L.n >> 3) ? D[(j & 7) * 8 + (L.n & 7)] : 0.f;
+    L.zr[c] = 0;
+  }
+}
+
+struct WaveLds8 {
+  float c[4][64];
+};
+
+template <int XF>
+__global__ __launch_bounds__(kGroupThreads) void k_sense8(const ImgDev* __restrict__ imgs,
+                                                         const Tile* __restrict__ tiles, int ntiles,
+                                                         const uint8_t* __restrict__ px,
+                                                         const int32_t* __restrict__ k_all,
+                                                         const int64_t* __restrict__ off_all,
+                                                         float* __restrict__ y) {
+  __shared__ WaveLds8 lds[kWavesPerGroup];
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= ntiles) return;
+  const Tile tl = tiles[wave];
+  const ImgDev im = imgs[tl.img];
+  Lane16 L;
+  lane8x4_init<XF>(L);
+  const int lane = threadIdx.x & 63;
+  // operand side: block quadrant and pixel row / column of this lane
+  const int xq = 2 * (L.n >> 3) + (L.g >> 1), xrow = L.n & 7, xcol = 4 * (L.g & 1);
+  // output side: block quadrant and zigzag rank of coefficient r
+  const int oq = 2 * (L.g >> 1) + (L.n >> 3);
+  int zr[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) zr[r] = c_zzrank8[(4 * (L.g & 1) + r) * 8 + (L.n & 7)];
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, 7 * im.pitch + 8 * tl.count);
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(y + im.meas_off, (int)(4 * im.n_meas));
+  const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(off_all + im.blk_off + tl.first, 8 * tl.count);
+  const int32_t kl = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rk, 4 * lane, 0, 0);
+  const int32_t rl = (int32_t)(__builtin_amdgcn_raw_buffer_load_b32(ro, 8 * lane, 0, 0) - (uint32_t)im.meas_off);
+  WaveLds8& buf = lds[wave_in_group()];
+  for (int b0 = 0; b0 < tl.count; b0 += 4) {
+    const int bx = b0 + xq;
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(
+        rp, bx < tl.count ? (uint32_t)(xrow * im.pitch + 8 * bx + xcol) : 0xffffffffu, 0, 0);
+    float a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = (float)((w >> (8 * c)) & 0xffu);
+    const f32x4 C = dct16_fwd(a, L);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) buf.c[oq][zr[r]] = C[r];
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = b0 + q;
+      if (b < tl.count) {
+        const int kk = __builtin_amdgcn_readlane(kl, b);
+        const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(rl, b);
+        const uint32_t voff = lane < kk ? rel4 + 4u * (uint32_t)lane : 0xffffffffu;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(buf.c[q][lane]), ry, voff, 0, 0);
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+template <int XF>
+__global__ __launch_bounds__(kGroupThreads) void k_reconstruct8(const ImgDev* __restrict__ imgs,
+                                                               const Tile* __restrict__ tiles, int ntiles,
+                                                               const float* __restrict__ y,
+                                                               const int32_t* __restrict__ k_all,
+                                                               const int64_t* __restrict__ off_all,
+                                                               float* __restrict__ out) {
+  typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+  __shared__ WaveLds8 lds[kWavesPerGroup];
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= ntiles) return;
+  const Tile tl = tiles[wave];
+  const ImgDev im = imgs[tl.img];
+  Lane16 L;
+  lane8x4_init<XF>(L);
+  const int lane = threadIdx.x & 63;
+  const int xq = 2 * (L.n >> 3) + (L.g >> 1), xrow = L.n & 7, xcol = 4 * (L.g & 1);
+  const int oq = 2 * (L.g >> 1) + (L.n >> 3);
+  int zr[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) zr[c] = c_zzrank8[(4 * (L.g & 1) + c) * 8 + (L.n & 7)];
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(y + im.meas_off, (int)(4 * im.n_meas));
+  const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(off_all + im.blk_off + tl.first, 8 * tl.count);
+  const __amdgpu_buffer_rsrc_t rout = make_rsrc(out + tl.out_base, 4 * (7 * im.Wc + 8 * tl.count));
+  const int32_t kl = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rk, 4 * lane, 0, 0);
+  const int32_t rl = (int32_t)(__builtin_amdgcn_raw_buffer_load_b32(ro, 8 * lane, 0, 0) - (uint32_t)im.meas_off);
+  WaveLds8& buf = lds[wave_in_group()];
+  for (int b0 = 0; b0 < tl.count; b0 += 4) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = b0 + q;
+      const int kk = b < tl.count ? __builtin_amdgcn_readlane(kl, b) : 0;
+      const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(rl, b < tl.count ? b : 0);
+      const uint32_t voff = lane < kk ? rel4 + 4u * (uint32_t)lane : 0xffffffffu;
+      buf.c[q][lane] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ry, voff, 0, 0));
+    }
+    wave_lds_sync();
+    float e[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) e[c] = buf.c[oq][zr[c]];
+    wave_lds_sync();
+    const f32x4 X = idct16_inv(e, L);
+    const int bx = b0 + xq;
+    const uint32_t off = bx < tl.count ? 4u * (uint32_t)(xrow * im.Wc + 8 * bx + xcol) : 0xffffffffu;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X), rout, off, 0, kStoreNT);
   }
 }
 
