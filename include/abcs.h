@@ -83,9 +83,8 @@ typedef enum abcs_transform {
 } abcs_transform;
 
 /* Arithmetic of the B = 16 DCT transforms in abcs_sense and
- * abcs_reconstruct (B = 8 always uses float32 operands with float64 sums;
- * B = 32, and B = 16 Walsh-Hadamard images, always use the float32 matrix
- * cores).  The 16-bit modes run on the matrix cores with float32 sums; the
+ * abcs_reconstruct (B = 8 and 32, and B = 16 Walsh-Hadamard images, always
+ * use the float32 matrix cores).  The 16-bit modes run on the matrix cores with float32 sums; the
  * "x3" modes split each operand that is not exact in 16 bits into a high and a
  * low part and keep every product but low x low (about float32 accuracy); the
  * single-pass modes round the operands once.  Budgets (abcs_budget) never
@@ -135,9 +134,9 @@ typedef struct abcs_plan abcs_plan; /* opaque */
  * Errors: EINVAL (null pointer, n < 0, pitch/offset/alignment), EDOMAIN
  * (C_R outside (0,1], no whole block, M = 0, BBV with C_R > 0.5, BBV samples
  * exceeding M), EINVAL (unknown transform), EUNSUPPORTED (B not 8, 16 or
- * 32), EHIP.  Images with B = 16 (DCT or Walsh-Hadamard), and the sensing and
- * inverse transform of B = 32, run on the matrix cores; the rest of B = 8
- * and 32 runs on the vector ALUs (same results and error bars: budgets and
+ * 32), EHIP.  Sensing and the inverse transform run on the matrix cores for
+ * every B; the DD statistics and the IDA transform step of B = 8 and 32 run
+ * on the vector ALUs (same results and error bars for every B: budgets and
  * index sets exact, DD statistics evaluated in float64). */
 int abcs_plan_create(const abcs_image* h_imgs, int n, abcs_plan** out);
 void abcs_plan_destroy(abcs_plan* plan);
