@@ -1,5 +1,7 @@
-"""GPU parity for block sizes 8 and 32 (the vector-ALU path) and for plans
-that mix B = 8, 16 and 32, against the FP64 oracle.
+"""GPU parity for block sizes 8 and 32 and for plans that mix B = 8, 16 and
+32, against the FP64 oracle.  Sensing and the inverse transform run on the
+matrix cores (B = 8: four blocks per 16x16 transform; B = 32: 2x2 tiles of
+16x16), the DD statistics and the IDA step on the vector ALUs.
 
 Bars as for B = 16: budgets, statistics and offsets bit-exact; decoded pixels
 within 1e-3 of the oracle's decoding of the same measurements.  y: within
@@ -140,3 +142,33 @@ def test_denoisers_on_block_8_plans():
     ws2 = torch.empty(g.ida_workspace_bytes(run.plan, "cnn"), dtype=torch.uint8, device=dev)
     with pytest.raises(g.AbcsError, match="EUNSUPPORTED"):
         g.ida_refine(run.plan, run.y, run.k, run.off, x, 1, 2.0, "cnn", params=params, workspace=ws2)
+
+
+@pytest.mark.parametrize("B", [8, 32])
+def test_short_tiles_every_remainder(B):
+    """Block rows of 1 .. 7 blocks and tiles whose block count leaves every
+    remainder modulo 4 (the B = 8 kernels transform four blocks at a time),
+    both transforms, all three rules, one plan."""
+    widths = [B * n for n in (1, 2, 3, 4, 5, 6, 7, 17, 18, 19)]
+    imgs = [synth.synth_image(1900 + i, 2 * B + 3, w + (i % 3)) for i, w in enumerate(widths)]
+    px, d = pack_images(imgs, pitch_pad=4)
+    entries, cases = [], []
+    for i, img in enumerate(imgs):
+        m = ("zz", "bbv", "dd")[i % 3]
+        cr = (0.3, 0.45, 0.2)[i % 3]
+        entries.append(dict(d[i], block=B, subrate=cr, method=m, transform="dct"))
+        cases.append((i, "dct", m, cr))
+        entries.append(dict(d[i], block=B, subrate=cr, method="dd", transform="wht"))
+        cases.append((i, "wht", "dd", cr))
+    run = Run(px, entries).budget().sense().reconstruct().fetch()
+    for j, (i, xf, m, cr) in enumerate(cases):
+        img = imgs[i]
+        got = run.image(j)
+        k, stat = orc.budget(img, B, cr, orc.METHOD_NAMES[m], transform=xf)
+        assert np.array_equal(got["k"], k), f"k (entry {j}: {img.shape}, {xf}, {m})"
+        assert np.array_equal(got["stat"], stat), f"stat (entry {j})"
+        y = orc.sense(img, B, k, transform=xf)
+        if y.size:
+            assert np.max(np.abs(got["y"] - y)) < Y_TOL[B], f"y (entry {j}: {img.shape}, {xf})"
+        rec = orc.reconstruct(got["y"].astype(np.float64), B, k, *img.shape, transform=xf)
+        assert np.max(np.abs(got["out"] - rec)) < PX_TOL, f"pixels (entry {j}: {img.shape}, {xf})"
