@@ -56,9 +56,11 @@ __device__ __forceinline__ void bbv_stats_thread(const ImgDev* __restrict__ imgs
 // ---------------------------------------------------------------------------
 // DD n_i: one wavefront per tile of 16x16 blocks.  A compensated float16
 // MFMA transform (dct16_fwd_f16k32) decides |c| > T for every coefficient
-// further than kDDGuard from T; the rest are recomputed in float64 in the
-// fixed order of dct16_coef_f64 from the block staged in LDS, so the counts
-// are those of the float64 definition whatever the screening arithmetic.
+// further than kDDGuard from T; the rest are recomputed in float64 from the
+// block staged in LDS in one fixed order, T[r] = sum_j X[r][j] D[v][j] (j
+// ascending), c = sum_r D[u][r] T[r] (r ascending), every product and sum
+// rounded on its own, so the counts are those of the float64 definition
+// whatever the screening arithmetic.
 //
 // kDDGuard bounds the screening error of a coefficient (u = 2^-24 the float32
 // unit roundoff, with every float32 sum of n terms taken to err by at most
@@ -80,20 +82,51 @@ constexpr float kDDGuard = 0.05f;
 // flushed before a block whenever fewer than 128 slots are free.
 constexpr int kDDListCap = 256;
 
-// Settles queued coefficients: lane j of each batch recomputes entry j in
-// float64 from the staged pixels and counts it for its block if |c| > T.
+// Settles queued coefficients in float64, four per pass: the 16 lanes of
+// quarter j of the wave take entry base + j, lane r of the quarter forms row
+// r's inner sum t_r = sum_y D[v][y] X[r][y] over the columns in order, and
+// the quarter's first lane adds D[u][r] t_r over the rows in order: the
+// fixed order above, products rounded, then added, no contraction.  The
+// count goes to the entry's block if |c| > T.  A pass costs about 130
+// instructions whatever its number of entries, and most tiles queue only a
+// few, so spreading one entry over 16 lanes beats one entry per lane (a
+// dependent chain of 256 products).
 __device__ __forceinline__ void dd_flush(const uint16_t* list, int n, const uint32_t* st, const double* sD, int T,
-                                         int32_t* ucnt) {
-  const int lane = threadIdx.x & 63;
+                                         int32_t* ucnt, double* tp) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & 63, j = lane >> 4, r = lane & 15;
   wave_lds_sync();
-  for (int base = 0; base < n; base += 64) {
-    if (base + lane < n) {
-      const int e = list[base + lane];
-      const int b = e >> 8;
-      if (fabs(dct16_coef_f64(st + 4 * b, sD, (e >> 4) & 15, e & 15)) > (double)T) atomicAdd(&ucnt[b], 1);
+  for (int base = 0; base < n; base += 4) {
+    const bool act = base + j < n;
+    const int e = act ? (int)list[base + j] : 0;
+    const int b = e >> 8, u = (e >> 4) & 15, v = e & 15;
+    double t = 0.0;
+    if (act) {
+      const uint32_t* row = st + r * (kPxRow / 4) + 4 * b;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t w = row[q];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double x = (double)((w >> (8 * c)) & 0xffu);
+          const double p = x * sD[v * 16 + 4 * q + c];
+          t = t + p;
+        }
+      }
     }
+    tp[lane] = t;
+    wave_lds_sync();
+    if (act && r == 0) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const double p = sD[u * 16 + i] * tp[lane + i];
+        acc = acc + p;
+      }
+      if (fabs(acc) > (double)T) atomicAdd(&ucnt[b], 1);
+    }
+    wave_lds_sync();
   }
-  wave_lds_sync();
 }
 
 template <int XF>
@@ -104,6 +137,7 @@ __device__ __forceinline__ void dd_stats_group(const ImgDev* __restrict__ imgs, 
   __shared__ PxStage stage[kWavesPerGroup];
   __shared__ uint16_t ulist[kWavesPerGroup][kDDListCap];
   __shared__ int32_t ucount[kWavesPerGroup][kTileBlocks];
+  __shared__ double tpart[kWavesPerGroup][64];
   sD[threadIdx.x] = Basis16<XF>::Dd()[threadIdx.x];
   __syncthreads();
   const int wave = group * kWavesPerGroup + wave_in_group();
@@ -136,7 +170,7 @@ __device__ __forceinline__ void dd_stats_group(const ImgDev* __restrict__ imgs, 
 #pragma unroll 2
   for (int b = 0; b < kTileBlocks; ++b) {
     if (nlist > kDDListCap - 128) {
-      dd_flush(list, nlist, st, sD, im.T, ucnt);
+      dd_flush(list, nlist, st, sD, im.T, ucnt, tpart[wave_in_group()]);
       nlist = 0;
     }
     const uint32_t pw = staged_px(st, b, L);
@@ -168,7 +202,7 @@ __device__ __forceinline__ void dd_stats_group(const ImgDev* __restrict__ imgs, 
     }
     if (lane == b) my_stat = cnt;
   }
-  if (nlist > 0) dd_flush(list, nlist, st, sD, im.T, ucnt);
+  if (nlist > 0) dd_flush(list, nlist, st, sD, im.T, ucnt, tpart[wave_in_group()]);
   if (lane < kTileBlocks) my_stat += ucnt[lane];
   if (lane < tl.count) stat[im.blk_off + tl.first + lane] = my_stat;
 }

@@ -328,40 +328,4 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
   return v;
 }
 
-// Float64 DCT coefficient (u, v) of a 16x16 uint8 block in the fixed order
-// T[r] = sum_j X[r][j] D[v][j] (j ascending), C = sum_r D[u][r] T[r]
-// (r ascending), every product and sum rounded on its own.  Used to settle
-// DD threshold decisions that the float32 path cannot decide.  `words` is the
-// block in a pixel stage (PxStage, offset to the block): word r kPxRow / 4 + g
-// holds pixels (r, 4g .. 4g+3), one per byte; `D` is the float64 basis.  The 16 row
-// sums are independent and advance together, so the dependent chain is 16 + 16
-// additions long.
-__device__ __forceinline__ double dct16_coef_f64(const uint32_t* words, const double* D, int u, int v) {
-#pragma clang fp contract(off)
-  double t[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) t[r] = 0.0;
-  // one column group at a time keeps 16 pixel words and 4 basis values live
-#pragma unroll 1
-  for (int q = 0; q < 4; ++q) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const uint32_t w = words[r * (kPxRow / 4) + q];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double x = (double)((w >> (8 * c)) & 0xffu);
-        const double p = x * D[v * 16 + 4 * q + c];
-        t[r] = t[r] + p;
-      }
-    }
-  }
-  double acc = 0.0;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const double p = D[u * 16 + r] * t[r];
-    acc = acc + p;
-  }
-  return acc;
-}
-
 }  // namespace abcs
