@@ -12,6 +12,8 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in VGPRs (no AGPR round trip before each use)
+    "-mllvm", "--amdgpu-mfma-vgpr-form",
 ]
 
 

@@ -25,11 +25,12 @@ def _check(imgs, reqs):
         assert np.array_equal(got["off"], orc.offsets(k)), f"offsets (request {j})"
 
 
-@pytest.mark.parametrize("size,B", [((1024, 768), 16), ((1024, 1024), 8), ((2048, 2048), 8)])
+@pytest.mark.parametrize("size,B", [((512, 512), 16), ((496, 528), 16), ((400, 656), 16), ((1024, 768), 16), ((1024, 1024), 8), ((2048, 2048), 8)])
 def test_apportion_kernels_by_image_size(size, B):
-    """Largest images of 3072 (registers), 16,384 and 65,536 blocks
-    (histogram), with a small image beside them, so that one plan mixes block
-    counts."""
+    """Largest images of 1023, 1024, 1025 and 3072 blocks (registers: some
+    threads' last blocks empty, or all full), 16,384 and 65,536 blocks
+    (histogram), with a small image beside them, so that one plan mixes
+    block counts."""
     big = synth.synth_image(4000, *size)
     small = synth.synth_image(4001, 64, 80)
     reqs = [(0, B, 0.1, "bbv"), (0, B, 0.35, "dd"), (0, B, 0.5, "bbv"), (1, 16, 0.2, "dd"), (1, 8, 0.3, "zz")]
@@ -46,3 +47,16 @@ def test_apportion_global_memory_kernel():
     """An image of more than 131,072 blocks (2048 x 4608 at B = 8: 147,456)."""
     big = synth.synth_image(4003, 2048, 4608)
     _check([big], [(0, 8, 0.3, "bbv"), (0, 8, 0.25, "dd")])
+
+
+def test_apportion_uniform_weights_and_ties():
+    """A flat image (every BBV weight 0, so the weights count as equal and
+    all remainders tie) and a line pattern (few distinct weights, many equal
+    remainders), at several rates."""
+    flat = np.full((512, 512), 97, dtype=np.uint8)
+    two = np.zeros((256, 512), dtype=np.uint8)
+    two[:, ::32] = 255
+    two[::48, :] = 200
+    reqs = [(0, 16, 0.1, "bbv"), (0, 16, 0.45, "bbv"), (0, 16, 0.3, "dd"), (1, 16, 0.2, "bbv"), (1, 16, 0.25, "dd"),
+            (1, 16, 0.4, "dd")]
+    _check([flat, two], reqs)
