@@ -67,16 +67,16 @@ def algorithmic_bytes(plan, kind):
 # HBM traffic of a kernel on this workload: rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads for
 # a plain device copy of 1 GiB (`bench.py --copy-probe 1024`).  A reading holds
-# only for the kernel source it was taken on, so it is keyed by the SHA-256 of
-# the files that define the kernel; after any change the figure is null until
-# the counters are taken again.
+# only for the kernel it was taken on, so it is keyed by the SHA-256 of the
+# files that define the kernel and of the build script (its compiler flags);
+# after any change the figure is null until the counters are taken again.
 COPY_KIB = 1048576.0
 TRAFFIC = {
     "reconstruct": dict(
-        sources=("common.hpp", "transform16.hpp", "sense_kernels.hpp"),
-        sha256="133229ccb0b17bf56307791c43d5603572a737ec02b3ea94f532746f106f11c0",
-        fetch_kib=98084.91, write_kib=655510.03,
-        copy_fetch_kib=524301.21, copy_write_kib=1048576.0),
+        sources=("csrc/common.hpp", "csrc/transform16.hpp", "csrc/sense_kernels.hpp", "build.py"),
+        sha256="9668c636727d01af0d042c049d7c47cbbdad6b99955a545ffc2ef7d519e986a1",
+        fetch_kib=98084.84, write_kib=655553.97,
+        copy_fetch_kib=524301.13, copy_write_kib=1048576.0),
 }
 
 
@@ -88,7 +88,7 @@ def measured_traffic(kind):
         return None
     h = hashlib.sha256()
     for f in t["sources"]:
-        with open(os.path.join(ROOT, "paper_2001_09632_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_2001_09632_amd", f), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest() != t["sha256"]:
         return None
