@@ -84,15 +84,17 @@ constexpr int kDDListCap = 256;
 
 // Settles queued coefficients in float64, four per pass: the 16 lanes of
 // quarter j of the wave take entry base + j, lane r of the quarter forms row
-// r's inner sum t_r = sum_y D[v][y] X[r][y] over the columns in order, and
-// the quarter's first lane adds D[u][r] t_r over the rows in order: the
-// fixed order above, products rounded, then added, no contraction.  The
-// count goes to the entry's block if |c| > T.  A pass costs about 130
-// instructions whatever its number of entries, and most tiles queue only a
-// few, so spreading one entry over 16 lanes beats one entry per lane (a
-// dependent chain of 256 products).
-__device__ __forceinline__ void dd_flush(const uint16_t* list, int n, const uint32_t* st, const double* sD, int T,
-                                         int32_t* ucnt, double* tp) {
+// r's inner sum t_r = sum_y D[v][y] X[r][y] over the columns in order and the
+// product D[u][r] t_r, and the products are added over the rows in order
+// (read across the quarter by shuffles): the fixed order above, products
+// rounded, then added, no contraction.  The count goes to the entry's block
+// if |c| > T.  A pass costs a fixed ~200 instructions whatever its number of
+// entries, and most tiles queue only a few, so spreading one entry over 16
+// lanes beats one entry per lane (a dependent chain of 256 products).  `D`
+// is the float64 basis in constant memory: the kernel keeps no LDS copy, so
+// that eight workgroups fit on a compute unit.
+__device__ __forceinline__ void dd_flush(const uint16_t* list, int n, const uint32_t* st,
+                                         const double* __restrict__ D, int T, int32_t* ucnt) {
 #pragma clang fp contract(off)
   const int lane = threadIdx.x & 63, j = lane >> 4, r = lane & 15;
   wave_lds_sync();
@@ -103,43 +105,35 @@ __device__ __forceinline__ void dd_flush(const uint16_t* list, int n, const uint
     double t = 0.0;
     if (act) {
       const uint32_t* row = st + r * (kPxRow / 4) + 4 * b;
-#pragma unroll
+      // one column group at a time: four basis values live, not sixteen
+#pragma unroll 1
       for (int q = 0; q < 4; ++q) {
         const uint32_t w = row[q];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const double x = (double)((w >> (8 * c)) & 0xffu);
-          const double p = x * sD[v * 16 + 4 * q + c];
+          const double p = x * D[v * 16 + 4 * q + c];
           t = t + p;
         }
       }
     }
-    tp[lane] = t;
-    wave_lds_sync();
-    if (act && r == 0) {
-      double acc = 0.0;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const double p = sD[u * 16 + i] * tp[lane + i];
-        acc = acc + p;
-      }
-      if (fabs(acc) > (double)T) atomicAdd(&ucnt[b], 1);
-    }
-    wave_lds_sync();
+    const double pr = D[u * 16 + r] * t;
+    double acc = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < 16; ++i) acc = acc + __shfl(pr, (lane & 48) + i, 64);
+    if (act && r == 0 && fabs(acc) > (double)T) atomicAdd(&ucnt[b], 1);
   }
+  wave_lds_sync();
 }
 
 template <int XF>
 __device__ __forceinline__ void dd_stats_group(const ImgDev* __restrict__ imgs, const Tile* __restrict__ tiles,
                                                int ntiles, const uint8_t* __restrict__ px,
                                                int32_t* __restrict__ stat, int group) {
-  __shared__ double sD[256];
   __shared__ PxStage stage[kWavesPerGroup];
   __shared__ uint16_t ulist[kWavesPerGroup][kDDListCap];
   __shared__ int32_t ucount[kWavesPerGroup][kTileBlocks];
-  __shared__ double tpart[kWavesPerGroup][64];
-  sD[threadIdx.x] = Basis16<XF>::Dd()[threadIdx.x];
-  __syncthreads();
+  const double* Dd = Basis16<XF>::Dd();
   const int wave = group * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
   const Tile tl = tiles[wave];
@@ -170,7 +164,7 @@ __device__ __forceinline__ void dd_stats_group(const ImgDev* __restrict__ imgs, 
 #pragma unroll 2
   for (int b = 0; b < kTileBlocks; ++b) {
     if (nlist > kDDListCap - 128) {
-      dd_flush(list, nlist, st, sD, im.T, ucnt, tpart[wave_in_group()]);
+      dd_flush(list, nlist, st, Dd, im.T, ucnt);
       nlist = 0;
     }
     const uint32_t pw = staged_px(st, b, L);
@@ -202,7 +196,7 @@ __device__ __forceinline__ void dd_stats_group(const ImgDev* __restrict__ imgs, 
     }
     if (lane == b) my_stat = cnt;
   }
-  if (nlist > 0) dd_flush(list, nlist, st, sD, im.T, ucnt, tpart[wave_in_group()]);
+  if (nlist > 0) dd_flush(list, nlist, st, Dd, im.T, ucnt);
   if (lane < kTileBlocks) my_stat += ucnt[lane];
   if (lane < tl.count) stat[im.blk_off + tl.first + lane] = my_stat;
 }
