@@ -244,8 +244,10 @@ __device__ __forceinline__ T wave_sum_t(T v) {
 }
 
 // k_apportion keeps an image's blocks in global memory; it serves images of
-// more than 8192 blocks (1024 threads per image).  Smaller images use
-// k_apportion_reg below, which holds them in registers.
+// more than kApHistMaxBlocks blocks (1024 threads per image).  Images of at
+// most 8192 blocks use k_apportion_reg below, which holds them in registers
+// (4 or 8 per thread), and those in between k_apportion_hist, which works on
+// a histogram of the weights.
 
 template <int NW, typename T>
 __device__ T group_sum(T v, T* sh) {
