@@ -74,9 +74,9 @@ COPY_KIB = 1048576.0
 TRAFFIC = {
     "reconstruct": dict(
         sources=("csrc/common.hpp", "csrc/transform16.hpp", "csrc/sense_kernels.hpp", "build.py"),
-        sha256="9668c636727d01af0d042c049d7c47cbbdad6b99955a545ffc2ef7d519e986a1",
-        fetch_kib=98084.84, write_kib=655553.97,
-        copy_fetch_kib=524301.13, copy_write_kib=1048576.0),
+        sha256="09a4468b9463b3d0014580f20071dd38097e85d3d6f70f786737b8be6cf37784",
+        fetch_kib=98078.44, write_kib=655519.97,
+        copy_fetch_kib=524301.26, copy_write_kib=1048576.0),
 }
 
 

@@ -210,11 +210,20 @@ __device__ __forceinline__ f32x4 dct16_fwd_f16k32(const float a[4], const Lane16
   const f16x8 x = __builtin_shufflevector(x4, x4, 0, 1, 2, 3, 0, 1, 2, 3);
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   const f32x4 t = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, K.d_hilo, zero, 0, 0, 0);
-  const float tv[4] = {t[0], t[1], t[2], t[3]};
-  u16x4 th, tl;
-  split16<false>(tv, th, tl);
-  const f16x8 tt = __builtin_shufflevector(__builtin_bit_cast(f16x4, th), __builtin_bit_cast(f16x4, tl), 0, 1, 2, 3,
-                                           4, 5, 6, 7);
+  // hi = T rounded to float16, packed two to a register once; lo = T - hi
+  // rounded to float16, with hi widened from those packed registers (the
+  // values of split16, without converting T to float16 a second time)
+  typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const f16x2 h01 = __builtin_convertvector((f32x2){t[0], t[1]}, f16x2);
+  const f16x2 h23 = __builtin_convertvector((f32x2){t[2], t[3]}, f16x2);
+  const f32x2 w01 = __builtin_convertvector(h01, f32x2);
+  const f32x2 w23 = __builtin_convertvector(h23, f32x2);
+  const f16x2 l01 = __builtin_convertvector((f32x2){t[0] - w01[0], t[1] - w01[1]}, f16x2);
+  const f16x2 l23 = __builtin_convertvector((f32x2){t[2] - w23[0], t[3] - w23[1]}, f16x2);
+  const f16x4 th = __builtin_shufflevector(h01, h23, 0, 1, 2, 3);
+  const f16x4 tl = __builtin_shufflevector(l01, l23, 0, 1, 2, 3);
+  const f16x8 tt = __builtin_shufflevector(th, tl, 0, 1, 2, 3, 4, 5, 6, 7);
   const f32x4 out = __builtin_amdgcn_mfma_f32_16x16x32_f16(K.d_hihi, tt, zero, 0, 0, 0);
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(K.d_lo0, tt, out, 0, 0, 0);
 }
