@@ -40,8 +40,12 @@ keep every weight finite.
 
 Parity: pinned by tests/test_oracle_bm3d.py: sigma = 0 and constant images
 are fixed points, the 3D transform is orthonormal, grouping on a crafted image
-reproduces hand-derived groups, and the denoiser lowers the error of a noisy
-image.  Its absolute quality on natural images is parity unpinned (the paper
+reproduces hand-derived groups, the Kaiser window equals its closed form
+I0(beta sqrt(1 - t^2)) / I0(beta), both stages' group weights (1 / (sigma^2
+N_har) and 1 / (sigma^2 ||W||^2)) reproduce a hand-computed aggregation of
+two overlapping single-patch groups (which reduces each stage to 2-D DCT
+shrinkage, computed there with scipy's DCT), and the denoiser lowers the
+error of a noisy image.  Its absolute quality on natural images is parity unpinned (the paper
 gives no BM3D numbers on available data).
 """
 

@@ -129,10 +129,15 @@ def forward(blob, v, sigma, keep=False):
     return (out, acts) if keep else out
 
 
-def loss_and_grad(blob, v, sigma, target):
-    """MSE loss of D(v)/255 against target/255 and its gradient blob."""
+def backward(blob, acts, out, target):
+    """MSE loss of out/255 against target/255 and its gradient blob, given
+    the forward cache: acts[0] the network input, acts[i] (i = 1..7) the
+    output of layer i after its ReLU (its sign gives the ReLU's derivative),
+    and `out` = v - 255 f.  The cache may come from another evaluation of the
+    same network (for example the values a device stored), so that each
+    layer's gradient can be checked from the same inputs."""
     layers = unpack(blob)
-    out, acts = forward(blob, v, sigma, keep=True)
+    out = np.asarray(out, dtype=np.float64)
     n = out.size
     diff = (out - np.asarray(target, dtype=np.float64)) / 255.0
     loss = float(np.sum(diff * diff) / n)
@@ -142,11 +147,17 @@ def loss_and_grad(blob, v, sigma, target):
     for i in range(len(layers) - 1, -1, -1):
         w, _ = layers[i]
         if i < len(layers) - 1:
-            g = g * (acts[i + 1] > 0.0)
-        grads[i] = conv3x3_weight_grad(acts[i], g)
+            g = g * (np.asarray(acts[i + 1]) > 0.0)
+        grads[i] = conv3x3_weight_grad(np.asarray(acts[i], dtype=np.float64), g)
         if i > 0:
             g = conv3x3_input_grad(g, w)
     return loss, pack(grads)
+
+
+def loss_and_grad(blob, v, sigma, target):
+    """MSE loss of D(v)/255 against target/255 and its gradient blob."""
+    out, acts = forward(blob, v, sigma, keep=True)
+    return backward(blob, acts, out, target)
 
 
 def adam_step(blob, m, v, grad, step, lr):

@@ -25,10 +25,11 @@ Parameter blob (float32 on the device, float64 here): W1 [64][3][3][2], b1
 beta [64]; then W17 [1][3][3][64], b17 [1].  Running statistics: for each
 middle layer mean [64] then variance [64].
 
-`round_act`, when given, is applied to every stored activation and to the
-pre-normalisation values, and `round_grad` to the gradients passed between
-layers (the GPU keeps all of these in bfloat16); by default every value is
-float64.
+Every value is float64.  `backward` takes the forward cache as an argument,
+so that the gradient can also be formed from activations and
+pre-normalisation values that another evaluation of the network stored
+(`cache_from_stored` derives the batch statistics and the normalised values
+from the stored pre-normalisation values, as the forward pass does).
 
 Parity: pinned by tests/test_oracle_dncnn.py: central finite differences of
 the loss (weights, gamma, beta), the normalised values' zero mean and unit
@@ -106,29 +107,31 @@ def init_running():
     return r.reshape(-1)
 
 
-def _ident(x):
-    return x
+def _normalise(z):
+    """Batch statistics of one normalisation (mean and biased variance per
+    channel over every pixel of the batch) and the normalised values."""
+    mu = z.mean(axis=(0, 1, 2))
+    var = ((z - mu) ** 2).mean(axis=(0, 1, 2))
+    return (mu, var), (z - mu) / np.sqrt(var + BN_EPS)
 
 
-def forward(blob, v, sigma, running=None, train=True, keep=False, round_act=None):
+def forward(blob, v, sigma, running=None, train=True, keep=False):
     """D(v) for a batch v [N,H,W], sigma [N].  train=True normalises with the
     batch statistics (returned in the cache as (mean, var) per layer);
     train=False uses `running`."""
-    rnd = round_act or _ident
     w1, b1, mids, w17, b17 = unpack(blob)
     run = None if running is None else np.asarray(running, dtype=np.float64).reshape(N_MID, 2, CH)
     x0 = ocnn.network_input(v, sigma)
-    a = rnd(np.maximum(ocnn.conv3x3(x0, w1, b1), 0.0))
+    a = np.maximum(ocnn.conv3x3(x0, w1, b1), 0.0)
     cache = {"x0": x0, "a": [a], "z": [], "zhat": [], "stats": []}
     for l, (w, g, b) in enumerate(mids):
-        z = rnd(ocnn.conv3x3(a, w, np.zeros(CH)))
+        z = ocnn.conv3x3(a, w, np.zeros(CH))
         if train:
-            mu = z.mean(axis=(0, 1, 2))
-            var = ((z - mu) ** 2).mean(axis=(0, 1, 2))
+            (mu, var), zhat = _normalise(z)
         else:
             mu, var = run[l, 0], run[l, 1]
-        zhat = (z - mu) / np.sqrt(var + BN_EPS)
-        a = rnd(np.maximum(g * zhat + b, 0.0))
+            zhat = (z - mu) / np.sqrt(var + BN_EPS)
+        a = np.maximum(g * zhat + b, 0.0)
         cache["z"].append(z)
         cache["zhat"].append(zhat)
         cache["stats"].append((mu, var))
@@ -138,15 +141,27 @@ def forward(blob, v, sigma, running=None, train=True, keep=False, round_act=None
     return (out, cache) if keep else out
 
 
-def loss_and_grad(blob, v, sigma, target, round_act=None, round_grad=None):
-    """Training mode: MSE of D(v)/255 against target/255, its gradient blob,
-    and the batch statistics [(mean, var)] of the 15 normalisations.
-    `round_grad`, when given, is applied to the gradients passed between
-    layers (at each normalisation's output and input), where the GPU stores
-    them in bfloat16."""
-    rg = round_grad or _ident
+def cache_from_stored(x0, a, z):
+    """Training-mode forward cache from stored values: the network input x0,
+    the 16 activations a_1 .. a_16 (after each ReLU) and the 15
+    pre-normalisation values; the batch statistics and normalised values are
+    derived from z as in `forward`."""
+    cache = {"x0": np.asarray(x0, dtype=np.float64), "a": [np.asarray(t, dtype=np.float64) for t in a],
+             "z": [np.asarray(t, dtype=np.float64) for t in z], "zhat": [], "stats": []}
+    for zl in cache["z"]:
+        st, zhat = _normalise(zl)
+        cache["stats"].append(st)
+        cache["zhat"].append(zhat)
+    return cache
+
+
+def backward(blob, cache, out, target):
+    """Training mode: MSE of out/255 against target/255 (out = D(v)), its
+    gradient blob, and the batch statistics [(mean, var)] of the 15
+    normalisations, from the forward cache."""
     w1, b1, mids, w17, b17 = unpack(blob)
-    out, c = forward(blob, v, sigma, train=True, keep=True, round_act=round_act)
+    c = cache
+    out = np.asarray(out, dtype=np.float64)
     n = out.size
     diff = (out - np.asarray(target, dtype=np.float64)) / 255.0
     loss = float(np.sum(diff * diff) / n)
@@ -156,21 +171,28 @@ def loss_and_grad(blob, v, sigma, target, round_act=None, round_grad=None):
     gmids = [None] * N_MID
     for l in range(N_MID - 1, -1, -1):
         w, gam, _ = mids[l]
-        gy = rg(ga * (c["a"][l + 1] > 0.0))              # through the ReLU
+        gy = ga * (c["a"][l + 1] > 0.0)                   # through the ReLU
         zhat = c["zhat"][l]
         _, var = c["stats"][l]
         cnt = gy.shape[0] * gy.shape[1] * gy.shape[2]
         ggam = (gy * zhat).sum(axis=(0, 1, 2))
         gbet = gy.sum(axis=(0, 1, 2))
         gzh = gy * gam
-        gz = rg((gzh - gzh.sum(axis=(0, 1, 2)) / cnt - zhat * (gzh * zhat).sum(axis=(0, 1, 2)) / cnt)
-                / np.sqrt(var + BN_EPS))
+        gz = ((gzh - gzh.sum(axis=(0, 1, 2)) / cnt - zhat * (gzh * zhat).sum(axis=(0, 1, 2)) / cnt)
+              / np.sqrt(var + BN_EPS))
         gw, _ = ocnn.conv3x3_weight_grad(c["a"][l], gz)
         gmids[l] = (gw, ggam, gbet)
         ga = ocnn.conv3x3_input_grad(gz, w)               # dL/da_l
-    g1 = rg(ga * (c["a"][0] > 0.0))
+    g1 = ga * (c["a"][0] > 0.0)
     gw1, gb1 = ocnn.conv3x3_weight_grad(c["x0"], g1)
     return loss, pack(gw1, gb1, gmids, gw17, gb17), c["stats"]
+
+
+def loss_and_grad(blob, v, sigma, target):
+    """Training mode: MSE of D(v)/255 against target/255, its gradient blob,
+    and the batch statistics [(mean, var)] of the 15 normalisations."""
+    out, c = forward(blob, v, sigma, train=True, keep=True)
+    return backward(blob, c, out, target)
 
 
 def update_running(running, stats):

@@ -87,3 +87,84 @@ def test_denoising_reduces_error(sigma):
     noisy = clean + np.random.default_rng(4).normal(0, sigma, size=clean.shape)
     out = bm3d.bm3d(noisy, sigma)
     assert metrics.psnr(out, clean) > metrics.psnr(noisy, clean) + 3.0
+
+
+def test_kaiser_window_closed_form():
+    # w[i] = I0(beta sqrt(1 - t^2)) / I0(beta), t = 2i/(n-1) - 1 (Kaiser's
+    # window; I0 from scipy), the 2-D window its outer product
+    from scipy.special import i0
+    t = 2.0 * np.arange(8) / 7.0 - 1.0
+    w = i0(bm3d.KAISER_BETA * np.sqrt(1.0 - t * t)) / i0(bm3d.KAISER_BETA)
+    assert np.allclose(bm3d.kaiser2d(), np.outer(w, w), rtol=1e-13, atol=0)
+    assert w[0] == pytest.approx(1.0 / i0(2.0)) and w[0] == pytest.approx(0.4386, abs=1e-4)
+
+
+def _single_member_image(seed):
+    """An 8 x 11 image of uniform noise: two reference positions (columns 0
+    and 3) whose groups hold only the reference (every other candidate
+    patch is far beyond both thresholds)."""
+    img = np.random.default_rng(seed).uniform(0, 255, size=(8, 11))
+    win = [img[:, x:x + 8] for x in range(4)]
+    for a in range(4):
+        for b in range(a + 1, 4):
+            assert np.sum((win[a] - win[b]) ** 2) / 64.0 > 2 * bm3d.TAU_HT
+    assert bm3d.ref_positions(11) == [0, 3] and bm3d.ref_positions(8) == [0]
+    return img
+
+
+def _aggregate_two(estimates, weights):
+    """Weighted Kaiser-window average of two 8 x 8 estimates at columns 0
+    and 3 of an 8 x 11 image (Kaiser window from its closed form)."""
+    from scipy.special import i0
+    t = 2.0 * np.arange(8) / 7.0 - 1.0
+    k = i0(2.0 * np.sqrt(1.0 - t * t)) / i0(2.0)
+    K = np.outer(k, k)
+    num, den = np.zeros((8, 11)), np.zeros((8, 11))
+    for x, e, w in zip((0, 3), estimates, weights):
+        num[:, x:x + 8] += w * K * e
+        den[:, x:x + 8] += w * K
+    return num / den
+
+
+def test_stage1_group_weight_is_inverse_surviving_count():
+    # groups of one patch: the 3-D transform is the patch's 2-D DCT (a
+    # length-1 Haar transform is the identity), so stage 1 is hard
+    # thresholding of each patch's DCT (scipy's orthonormal DCT here), and
+    # where the two patches overlap the estimate is their Kaiser-weighted
+    # average with weights 1 / (sigma^2 N_har)
+    from scipy.fft import dctn, idctn
+    sigma = 30.0
+    img = _single_member_image(8)
+    est, nhar = [], []
+    for x in (0, 3):
+        c = dctn(img[:, x:x + 8], norm="ortho")
+        c[np.abs(c) <= 2.7 * sigma] = 0.0
+        nhar.append(int(np.count_nonzero(c)))
+        est.append(idctn(c, norm="ortho"))
+    assert nhar[0] != nhar[1]
+    want = _aggregate_two(est, [1.0 / (sigma * sigma * n) for n in nhar])
+    got = bm3d.stage1(img, sigma)
+    assert np.max(np.abs(got - want)) < 1e-9
+    # the weights matter: equal weights give a visibly different image
+    assert np.max(np.abs(_aggregate_two(est, [1.0, 1.0]) - want)) > 0.1
+
+
+def test_stage2_group_weight_is_inverse_wiener_energy():
+    # groups of one patch again (matched on the stage-1 estimate `basic`):
+    # each patch's DCT is scaled by W = B^2 / (B^2 + sigma^2), B the DCT of
+    # the same patch of `basic`, and the group weight is 1 / (sigma^2 ||W||^2)
+    from scipy.fft import dctn, idctn
+    sigma = 40.0
+    basic = _single_member_image(9)
+    noisy = basic + np.random.default_rng(10).normal(0, sigma, size=basic.shape)
+    est, wts = [], []
+    for x in (0, 3):
+        b = dctn(basic[:, x:x + 8], norm="ortho")
+        W = b * b / (b * b + sigma * sigma)
+        est.append(idctn(W * dctn(noisy[:, x:x + 8], norm="ortho"), norm="ortho"))
+        wts.append(1.0 / (sigma * sigma * np.sum(W * W)))
+    assert abs(wts[0] / wts[1] - 1.0) > 0.05
+    want = _aggregate_two(est, wts)
+    got = bm3d.stage2(noisy, basic, sigma)
+    assert np.max(np.abs(got - want)) < 1e-9
+    assert np.max(np.abs(_aggregate_two(est, [1.0, 1.0]) - want)) > 0.01

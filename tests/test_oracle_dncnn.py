@@ -72,3 +72,21 @@ def test_folded_network_equals_inference(batch):
     a = dncnn.forward(blob, v, sigma, running=run, train=False)
     b = dncnn.forward_folded(dncnn.fold(blob, run), v, sigma)
     assert np.max(np.abs(a - b)) < 1e-9
+
+
+def test_backward_from_a_stored_cache(batch):
+    # the gradient formed from stored activations and pre-normalisation
+    # values (statistics re-derived from z) equals the one of the forward
+    # pass that produced them; a changed activation changes it
+    v, sigma, target, blob = batch
+    out, c = dncnn.forward(blob, v, sigma, train=True, keep=True)
+    loss, grad, stats = dncnn.loss_and_grad(blob, v, sigma, target)
+    c2 = dncnn.cache_from_stored(c["x0"], c["a"], c["z"])
+    loss2, grad2, stats2 = dncnn.backward(blob, c2, out, target)
+    assert loss2 == loss and np.array_equal(grad2, grad)
+    for (m1, v1), (m2, v2) in zip(stats, stats2):
+        assert np.array_equal(m1, m2) and np.array_equal(v1, v2)
+    a = [t.copy() for t in c["a"]]
+    a[3][0, 2, 2, :] += 0.5
+    _, grad3, _ = dncnn.backward(blob, dncnn.cache_from_stored(c["x0"], a, c["z"]), out, target)
+    assert not np.array_equal(grad3, grad)
