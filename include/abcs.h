@@ -66,10 +66,14 @@ typedef enum abcs_status {
 typedef enum abcs_denoiser {
   ABCS_DENOISE_IDENTITY = 0, /* D(v) = v: the loop without a denoiser        */
   ABCS_DENOISE_BM3D = 1,     /* plain BM3D (Dabov et al., ref [22])          */
-  ABCS_DENOISE_CNN = 2,      /* learned 8-layer 3x3 CNN (parameters passed)  */
+  ABCS_DENOISE_CNN = 2,      /* learned 8-layer 3x3 CNN; parameters: the
+                                weight blob (abcs_cnn_param_count floats)
+                                followed by the trained noise range [lo, hi]
+                                (2 floats)                                  */
   ABCS_DENOISE_DNCNN = 3     /* DnCNN-17 with batch normalisation (Section
-                                VI-4); parameters: the blob followed by the
-                                running statistics (abcs_dncnn_*_count)     */
+                                VI-4); parameters: the blob, the running
+                                statistics (abcs_dncnn_*_count), then the
+                                trained noise range [lo, hi]                */
 } abcs_denoiser;
 
 /* Sensing transform of an image (Section IV): the 2-D DCT-II, or the 2-D
@@ -127,8 +131,13 @@ typedef struct abcs_image {
 
 typedef struct abcs_plan abcs_plan; /* opaque */
 
-/* Validate a batch, compute its layout and upload its descriptor tables to the
- * current HIP device (allocates device memory once; not for the hot path).
+/* Validate a batch, compute its layout and upload every device table any call
+ * on the plan needs (descriptors, tile lists, the denoisers' reference grids
+ * and tiles, the bounds' tables) to the current HIP device in one allocation
+ * and one copy.  Plan creation and destruction are the only calls that
+ * allocate device memory or wait for the device (the first plan on a device
+ * also uploads the library's constant tables); every other call only
+ * enqueues kernels.
  * h_imgs: n descriptors (n >= 0), read only.  On success *out receives a plan
  * that must be released with abcs_plan_destroy.
  * Errors: EINVAL (null pointer, n < 0, pitch/offset/alignment), EDOMAIN
@@ -294,8 +303,11 @@ void ida_graph_destroy(abcs_ida_graph* graph);
  * search, groups of at most 16 / 32 (thresholds 2500 / 400 on ||P-Q||^2/64),
  * 8x8 DCT + Haar 3D transform, hard threshold 2.7 sigma, Wiener second stage,
  * Kaiser (beta 2) aggregation; results are bit-identical from run to run.
- * The CNN (parameters in d_params, see abcs_cnn_param_count) falls back to
- * BM3D for every image whose network output holds a non-finite value.
+ * The learned denoisers (parameters in d_params: the weights, then the noise
+ * range [lo, hi] the network was trained on) fall back to BM3D for every
+ * image whose sigma lies outside [lo, hi] (NaN included) or whose network
+ * output holds a non-finite value; the decision is taken on the device, and
+ * BM3D's kernels skip the other images.  A NaN sigma gives a NaN image.
  * d_ws: workspace of abcs_denoise_workspace_bytes(plan, denoiser) bytes,
  * 256-byte aligned (NULL allowed when that is 0). */
 size_t abcs_denoise_workspace_bytes(const abcs_plan* plan, int denoiser);
@@ -349,7 +361,7 @@ int abcs_denoise(const abcs_plan* plan, int denoiser, const void* d_params, cons
  *        entry do not matter.
  * Errors: EINVAL (unknown rule, null or misaligned buffer), ENOSPACE (pixel
  * buffer or workspace too small), EUNSUPPORTED (an image of 2^29 pixels or
- * more, or a Walsh-Hadamard image: the bounds are the DCT's), EHIP.  Allocates device tables on the first call with a plan. */
+ * more, or a Walsh-Hadamard image: the bounds are the DCT's), EHIP. */
 typedef enum abcs_threshold_rule { ABCS_THI = 1, ABCS_THB = 2 } abcs_threshold_rule;
 size_t abcs_threshold_workspace_bytes(const abcs_plan* plan);
 int abcs_threshold(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, int rule, int32_t* d_m,
@@ -378,7 +390,8 @@ int abcs_budget_correlation(const abcs_plan* plan, const int32_t* d_m, const int
  * statistics hold per middle layer mean [64] then variance [64]
  * (abcs_dncnn_running_count floats).  As a denoiser (ABCS_DENOISE_DNCNN) the
  * parameter pointer addresses the blob immediately followed by the running
- * statistics; normalisation is folded into the convolutions (inference). */
+ * statistics and the trained noise range [lo, hi]; normalisation is folded
+ * into the convolutions (inference). */
 size_t abcs_dncnn_param_count(void);
 size_t abcs_dncnn_running_count(void);
 
@@ -394,6 +407,40 @@ int abcs_dncnn_train_step(const abcs_plan* plan, float* d_params, float* d_adam_
                           float* d_running, int64_t step, float lr, const float* d_input, const float* d_sigma,
                           const float* d_target, float* d_loss, float* d_grad, void* d_ws, size_t ws_bytes,
                           void* stream);
+
+/* Where a workspace keeps the values a call leaves behind, for callers that
+ * inspect them (the parity tests check each layer of a training step, and
+ * BM3D's groups, from these values).  Byte offset and size within the
+ * workspace of the given kind for this plan:
+ *   ABCS_WS_CNN_TRAIN / ABCS_WS_DNCNN_TRAIN (abcs_cnn_train_step /
+ *   abcs_dncnn_train_step):
+ *     ACTIVATIONS: bfloat16, the output of every hidden layer after its ReLU
+ *                  (7 layers / 16 layers), layer after layer, each
+ *                  [pixel][64 channels] with pixels in plan order;
+ *     PRENORM:     (DnCNN only) bfloat16, the 15 middle layers' convolution
+ *                  outputs before normalisation, same layout;
+ *     OUTPUT:      float[pixels], the network output D(v).
+ *   ABCS_WS_DENOISE_BM3D (abcs_denoise with ABCS_DENOISE_BM3D):
+ *     GROUPS: int32, per reference patch (images in plan order, each image's
+ *             references in raster order of the 3-pixel grid) 33 entries: the
+ *             member count, then the members' positions y W' + x in group
+ *             order; after a call it holds the second (Wiener) stage's groups;
+ *     BASIC:  float[pixels], the first stage's estimate.
+ * The contents are those of the last call that used the workspace.
+ * Errors: EINVAL (null argument, unknown kind or part). */
+typedef enum abcs_workspace_kind {
+  ABCS_WS_CNN_TRAIN = 1,
+  ABCS_WS_DNCNN_TRAIN = 2,
+  ABCS_WS_DENOISE_BM3D = 3
+} abcs_workspace_kind;
+typedef enum abcs_workspace_part_id {
+  ABCS_PART_ACTIVATIONS = 1,
+  ABCS_PART_PRENORM = 2,
+  ABCS_PART_OUTPUT = 3,
+  ABCS_PART_GROUPS = 4,
+  ABCS_PART_BASIC = 5
+} abcs_workspace_part_id;
+int abcs_workspace_part(const abcs_plan* plan, int kind, int part, size_t* h_offset, size_t* h_bytes);
 
 /* Host copy of the float64 orthonormal DCT-II basis the library uses,
  * D[u*B + j] = s_u cos((2j+1) u pi / (2B)), for checking.  B in {8, 16, 32}. */

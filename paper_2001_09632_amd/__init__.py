@@ -13,4 +13,5 @@ from .api import (ZZ, BBV, DD, Plan, AbcsError, budget, sense, reconstruct,  # n
                   amp_refine, amp_workspace_bytes, ALGORITHMS, threshold,
                   threshold_workspace_bytes, budget_correlation, RULES, TRANSFORMS,
                   bbv_samples, ida_refine_bbv, dncnn_param_count, dncnn_running_count,
-                  dncnn_train_workspace_bytes, dncnn_train_step)
+                  dncnn_train_workspace_bytes, dncnn_train_step, workspace_part,
+                  denoiser_params)

@@ -17,7 +17,7 @@ EXPORTS = [
     "abcs_threshold_workspace_bytes", "abcs_threshold", "abcs_budget_correlation",
     "abcs_bbv_samples", "ida_refine_bbv",
     "abcs_dncnn_param_count", "abcs_dncnn_running_count", "abcs_dncnn_train_workspace_bytes",
-    "abcs_dncnn_train_step",
+    "abcs_dncnn_train_step", "abcs_workspace_part",
 ]
 
 
@@ -98,6 +98,7 @@ def lib():
     L.abcs_dncnn_train_workspace_bytes.argtypes = [vp]
     L.abcs_dncnn_train_workspace_bytes.restype = sz
     L.abcs_dncnn_train_step.argtypes = [vp, vp, vp, vp, vp, i64, ctypes.c_float, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.abcs_workspace_part.argtypes = [vp, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     L.ida_graph_destroy.argtypes = [vp]
     L.ida_graph_destroy.restype = None
     for name in EXPORTS:

@@ -219,6 +219,17 @@ def denoise(plan, x_in, sigma, x_out, denoiser="bm3d", params=None, workspace=No
                              _ptr(workspace), ws_bytes, _stream(stream)))
 
 
+def denoiser_params(weights, sigma_range):
+    """Parameter block of a learned denoiser as abcs_denoise / ida_refine take
+    it: the network's float32 weights (for DnCNN followed by its running
+    statistics), then the noise range [lo, hi] the network was trained on
+    (images whose sigma lies outside it are denoised by BM3D)."""
+    import numpy as np
+    lo, hi = sigma_range
+    return np.concatenate([np.asarray(weights, dtype=np.float32).reshape(-1),
+                           np.array([lo, hi], dtype=np.float32)])
+
+
 def cnn_param_count():
     return int(lib().abcs_cnn_param_count())
 
@@ -280,6 +291,20 @@ def dncnn_train_step(plan, params, adam_m, adam_v, running, step, lr, x_in, sigm
     check(lib().abcs_dncnn_train_step(plan.handle, _ptr(params), _ptr(adam_m), _ptr(adam_v), _ptr(running),
                                       int(step), float(lr), _ptr(x_in), _ptr(sigma), _ptr(target), _ptr(loss),
                                       _ptr(grad), _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+WS_KINDS = {"cnn_train": 1, "dncnn_train": 2, "bm3d": 3}
+WS_PARTS = {"activations": 1, "prenorm": 2, "output": 3, "groups": 4, "basic": 5}
+
+
+def workspace_part(plan, kind, part):
+    """abcs_workspace_part: (byte offset, bytes) of a named part of a
+    workspace ('cnn_train' / 'dncnn_train' / 'bm3d'; 'activations',
+    'prenorm', 'output', 'groups', 'basic')."""
+    off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+    check(lib().abcs_workspace_part(plan.handle, WS_KINDS[kind], WS_PARTS[part], ctypes.byref(off),
+                                    ctypes.byref(nb)))
+    return off.value, nb.value
 
 
 def dct_basis(block):

@@ -11,6 +11,12 @@
 // 1 / (sigma^2 max(||W||^2, 2^-16)); aggregation with an 8x8 Kaiser window
 // (beta = 2).  sigma <= 0 returns the input.
 //
+// Gating (the learned denoisers' fallback): every kernel takes `gate`, null or
+// int32[1 + n_imgs] with gate[0] != 0 when any image is to be denoised and
+// gate[1 + i] != 0 for each such image; a non-null gate makes the kernels skip
+// every other image (its output is left alone) and return at once when
+// gate[0] is 0, so an unused fallback costs only the launches.
+//
 // Aggregation is exact and order-independent: weights are scaled by sigma^2
 // (which cancels in num / den) and every contribution is rounded to a 64-bit
 // fixed-point integer (2^-24 units) before an integer atomic add, so results
@@ -75,13 +81,14 @@ template <int N2>
 __global__ __launch_bounds__(256) void k_bm3d_match(const ImgDev* __restrict__ imgs, const RefTile* __restrict__ tiles,
                                                    int ntiles, const float* __restrict__ src,
                                                    const float* __restrict__ sigma, float tau,
-                                                   int32_t* __restrict__ groups) {
+                                                   const int32_t* __restrict__ gate, int32_t* __restrict__ groups) {
   using namespace bm3d;
   constexpr int kSpan = 2 * kHalfWin + 1;    // 39 candidate offsets per axis
   constexpr int kSeg = kSpan + kN1 - 1;      // 46 pixels per search row
   __shared__ float win[kWin * kWin];
   if ((int)blockIdx.x >= ntiles) return;
   const RefTile tl = tiles[blockIdx.x];
+  if (gate && (gate[0] == 0 || gate[1 + tl.img] == 0)) return;
   const ImgDev im = imgs[tl.img];
   if (!(sigma[tl.img] > 0.f)) return;
   const int H = im.Hc, W = im.Wc;
@@ -265,6 +272,7 @@ __global__ __launch_bounds__(256) void k_bm3d_filter(const ImgDev* __restrict__ 
                                                     int ntiles, const float* __restrict__ noisy,
                                                     const float* __restrict__ basic, const float* __restrict__ sigma,
                                                     const int32_t* __restrict__ groups,
+                                                    const int32_t* __restrict__ gate,
                                                     unsigned long long* __restrict__ num,
                                                     unsigned long long* __restrict__ den) {
   using namespace bm3d;
@@ -274,6 +282,7 @@ __global__ __launch_bounds__(256) void k_bm3d_filter(const ImgDev* __restrict__ 
   __shared__ float sh[4][64];
   if ((int)blockIdx.x >= ntiles) return;
   const RefTile tl = tiles[blockIdx.x];
+  if (gate && (gate[0] == 0 || gate[1 + tl.img] == 0)) return;
   const ImgDev im = imgs[tl.img];
   const float sg = sigma[tl.img];
   if (!(sg > 0.f)) return;
@@ -372,26 +381,34 @@ __global__ __launch_bounds__(256) void k_bm3d_filter(const ImgDev* __restrict__ 
   }
 }
 
-// out = num / den for images with sigma > 0, out = in for sigma <= 0; images
-// whose sigma is NaN are skipped by every BM3D kernel.
+// out = num / den for images with sigma > 0, out = in for sigma <= 0, NaN
+// for a NaN sigma (no estimate: the matching and filtering kernels skip such
+// an image).
 __global__ __launch_bounds__(256) void k_bm3d_finish(const ImgDev* __restrict__ imgs, int n_imgs,
                                                     const float* __restrict__ sigma,
                                                     const unsigned long long* __restrict__ num,
                                                     const unsigned long long* __restrict__ den,
                                                     const float* __restrict__ in, float* __restrict__ out,
-                                                    int64_t pixels, const int32_t* __restrict__ pix_img) {
+                                                    int64_t pixels, const int32_t* __restrict__ pix_img,
+                                                    const int32_t* __restrict__ gate) {
+  if (gate && gate[0] == 0) return;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= pixels) return;
   const int im = pix_img[i >> kPixChunkShift];
+  if (gate && gate[1 + im] == 0) return;
   const float sg = sigma[im];
   if (sg > 0.f) {
     out[i] = (float)((double)(long long)num[i] / (double)(long long)den[i]);
-  } else if (!__builtin_isnan(sg)) {
+  } else if (sg <= 0.f) {
     out[i] = in[i];
-  }  // NaN: the image is not denoised by this call and its output is left alone
+  } else {
+    out[i] = sg;
+  }
 }
 
-__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* __restrict__ p, int64_t n) {
+__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* __restrict__ p, int64_t n,
+                                                 const int32_t* __restrict__ gate) {
+  if (gate && gate[0] == 0) return;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = 0ull;
 }

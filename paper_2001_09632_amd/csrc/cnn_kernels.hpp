@@ -348,19 +348,30 @@ __global__ __launch_bounds__(256) void k_cnn_last(const ImgDev* __restrict__ img
 // Fallback selection: sig_fb[i] = sigma[i] when image i's network output holds
 // a non-finite value, NaN otherwise (NaN makes the BM3D kernels skip the
 // image).  bad[] must be zero on entry.
+// Fallback gate of the learned denoisers (int32[1 + n], zero on entry):
+// gate[1 + i] = 1 for an image whose network output holds a non-finite
+// value, gate[0] = 1 when any image is flagged.
 __global__ __launch_bounds__(256) void k_cnn_check(const int32_t* __restrict__ pix_img, int64_t pixels,
-                                                  const float* __restrict__ out, int32_t* __restrict__ bad) {
+                                                  const float* __restrict__ out, int32_t* __restrict__ gate) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= pixels) return;
-  if (!__builtin_isfinite(out[p])) atomicOr(&bad[pix_img[p >> kPixChunkShift]], 1);
+  if (!__builtin_isfinite(out[p])) {
+    atomicOr(&gate[1 + pix_img[p >> kPixChunkShift]], 1);
+    atomicOr(&gate[0], 1);
+  }
 }
 
-__global__ void k_cnn_fallback_sigma(const int32_t* __restrict__ bad, const float* __restrict__ sigma, int n,
-                                     float* __restrict__ sig_fb, int32_t* __restrict__ bad_reset) {
+// Flags every image whose noise level lies outside the range the network was
+// trained on, range[0] <= sigma <= range[1] (a NaN sigma is outside).
+__global__ void k_cnn_sigma_gate(const float* __restrict__ sigma, int n, const float* __restrict__ range,
+                                 int32_t* __restrict__ gate) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  sig_fb[i] = bad[i] ? sigma[i] : __builtin_nanf("");
-  (void)bad_reset;
+  const float sg = sigma[i];
+  if (!(sg >= range[0] && sg <= range[1])) {
+    atomicOr(&gate[1 + i], 1);
+    atomicOr(&gate[0], 1);
+  }
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {

@@ -5,7 +5,10 @@ measurements y within 1e-2 absolute (float32 transform of [0, 255] pixels:
 with B = 16 every coefficient is a sum of 256 products whose magnitudes add
 up to at most 255 * 4 * 4, and two 16-term float32 accumulations keep the
 error below (2*16 + 2) * 2^-24 * 4080 < 1e-2); decoded pixels within 1e-3
-absolute of the oracle's decoding of the same measurements.
+absolute both of the oracle's decoding of the same measurements and, end to
+end, of the oracle's decoding of its own float64 measurements (the inverse
+transform is orthonormal, so the pixels' error has the same energy as the
+measurements', which in practice stay near 1e-4).
 """
 import numpy as np
 import pytest
@@ -28,8 +31,9 @@ def _check_image(run, i, img, block, cr, method, check_y=True, check_px=True):
     assert np.array_equal(got["stat"], stat), f"stat mismatch (image {i})"
     assert np.array_equal(got["off"], orc.offsets(k)), f"offset mismatch (image {i})"
     assert got["y"].size == k.sum()
-    if check_y:
+    if check_y or check_px:
         y = orc.sense(img, block, k)
+    if check_y:
         err = np.max(np.abs(got["y"] - y)) if y.size else 0.0
         assert err < Y_TOL, f"y error {err} (image {i})"
     if check_px:
@@ -37,6 +41,11 @@ def _check_image(run, i, img, block, cr, method, check_y=True, check_px=True):
         rec = orc.reconstruct(got["y"].astype(np.float64), block, k, H, W)
         err = np.max(np.abs(got["out"] - rec))
         assert err < PX_TOL, f"pixel error {err} (image {i})"
+        # end to end: the GPU's budget -> sense -> inverse transform against
+        # the oracle's decoding of the oracle's own measurements
+        rec = orc.reconstruct(y, block, k, H, W)
+        err = np.max(np.abs(got["out"] - rec))
+        assert err < PX_TOL, f"end-to-end pixel error {err} (image {i})"
 
 
 def test_single_image_bbv_256():

@@ -138,7 +138,7 @@ def test_denoisers_on_block_8_plans():
     g.ida_refine(run.plan, run.y, run.k, run.off, x, 2, 2.0, "bm3d", workspace=ws)
     torch.cuda.synchronize()
     assert np.all(np.isfinite(x.cpu().numpy()))
-    params = torch.from_numpy(ocnn.init_params(1).astype(np.float32)).to(dev)
+    params = torch.from_numpy(g.denoiser_params(ocnn.init_params(1), (0.5, 300.0))).to(dev)
     ws2 = torch.empty(g.ida_workspace_bytes(run.plan, "cnn"), dtype=torch.uint8, device=dev)
     with pytest.raises(g.AbcsError, match="EUNSUPPORTED"):
         g.ida_refine(run.plan, run.y, run.k, run.off, x, 1, 2.0, "cnn", params=params, workspace=ws2)

@@ -3,13 +3,13 @@ FP64 oracle: inference (normalisation folded into the convolutions) and one
 training step (batch statistics, gradients of every parameter, running
 statistics, Adam).
 
-The oracle runs with the weights rounded to bfloat16 and, where the kernels
-store them in bfloat16, with the activations and pre-normalisation values
-rounded too; the remaining difference is rounding order (float32 sums) and
-the bfloat16 rounding of the folded weights and of the gradients between
-layers.  Bars: network output within 5% of the largest |f| (1% on average);
-loss within 1%; per-layer gradients within twice the oracle's own rounding
-noise floor plus 0.05 (relative); running statistics within 1e-3 relative.
+The network's weights and activations are bfloat16 with float32 sums (the
+learned denoiser's arithmetic), so the reference is the float64 oracle on
+the weights rounded to bfloat16.  Inference: the folded network with its
+activations rounded to bfloat16, output within 5% of the largest |f| (1% on
+average).  Training: every layer is checked from the values the kernels
+stored (see the test's docstring); running statistics within 1e-5
+relative.
 """
 import numpy as np
 import pytest
@@ -19,9 +19,16 @@ from oracle import cnn as ocnn
 from oracle import dncnn
 
 from gpu_util import device
-from test_gpu_cnn import bf16_round
+from test_gpu_cnn import FWD_REL, bf16_round, fwd_bound, group_errors, split_layers, stored
 
 pytestmark = pytest.mark.gpu
+
+# Gradient bar per parameter group (element by element against the group's
+# largest magnitude, and relative L2): the bfloat16 rounding of the gradient
+# passed down through 15 normalisations compounds to about 1% at the first
+# layers (measured 1.4e-2 at b1, 1e-2 at W1, below 1e-3 from layer 16 up).
+GRAD_MAX = 3e-2
+GRAD_L2 = 3e-2
 
 
 def _blob(seed):
@@ -77,7 +84,7 @@ def test_dncnn_inference_matches_oracle():
     plan = _plan(2, 32, 48)
     xin = _put(plan, imgs)
     out = torch.full_like(xin, float("nan"))
-    prm = torch.from_numpy(np.concatenate([blob, run]).astype(np.float32)).to(device())
+    prm = torch.from_numpy(g.denoiser_params(np.concatenate([blob, run]), (0.0, np.inf))).to(device())
     ws = torch.empty(g.denoise_workspace_bytes(plan, "dncnn"), dtype=torch.uint8, device=device())
     g.denoise(plan, xin, torch.tensor(sig, dtype=torch.float32, device=device()), out, "dncnn", params=prm,
               workspace=ws)
@@ -106,32 +113,60 @@ def _train(blob, imgs, tgts, sig, lr=0.0, step=1):
                        torch.tensor(sig, dtype=torch.float32, device=dev), _put(plan, tgts), st["loss"], st["grad"],
                        workspace=ws)
     torch.cuda.synchronize()
-    return {k: t.cpu().numpy().astype(np.float64) for k, t in st.items()}
+    res = {k: t.cpu().numpy().astype(np.float64) for k, t in st.items()}
+    res["plan"], res["ws"] = plan, ws
+    return res
 
 
-def test_dncnn_training_step_matches_oracle():
-    """Gradients through 15 normalisations amplify rounding: the oracle itself,
-    with the inputs of its bfloat16 roundings perturbed by 1e-6 relative (a
-    few roundings in 10^4 flip), moves the first layer's gradient by ~0.4
-    relative.  The bar per parameter group is twice that noise floor plus
-    0.05, which at the last layers (floor ~0) means 5%."""
+def test_dncnn_layers_match_oracle_from_stored_values():
+    """Every layer is checked from the values the kernels stored in the
+    training workspace (activations a_1 .. a_16 and the 15 pre-normalisation
+    values z, bfloat16), so that an error in one layer cannot hide behind the
+    others and rounding does not compound through the depth of the network.
+    Forward: z_m equals the convolution of the stored a_m with the bfloat16
+    weights, a_(m+1) the normalisation (batch statistics of the stored z_m in
+    float64) and ReLU of z_m, each rounded to bfloat16, within one bfloat16
+    unit plus the float32 sums' error.  Backward: the oracle forms the
+    gradient from the same stored values (`dncnn.cache_from_stored`); each
+    parameter group must agree element by element within GRAD_MAX of its
+    largest magnitude and GRAD_L2 relative L2, W1 and b1 included.  What
+    remains is the kernels' bfloat16 rounding of the gradients passed
+    between layers (2^-9 relative per layer) and float32 sums."""
     blob = _blob(23)
     rng = np.random.default_rng(24)
     imgs = [synth.synth_image(210 + i, 32, 32).astype(np.float64) for i in range(3)]
     tgts = [np.clip(im + rng.normal(0, 15, im.shape), 0, 255) for im in imgs]
     sig = [20.0, 60.0, 35.0]
     got = _train(blob, imgs, tgts, sig)
+    plan, ws = got["plan"], got["ws"]
+    A = [np.stack(a) for a in split_layers(stored(plan, ws, "dncnn_train", "activations", 64), plan, 16)]
+    Z = [np.stack(z) for z in split_layers(stored(plan, ws, "dncnn_train", "prenorm", 64), plan, 15)]
+    outv = stored(plan, ws, "dncnn_train", "output", 1).reshape(len(imgs), *imgs[0].shape)
     rb = _rounded(blob)
-    l_ref, g_ref, stats = dncnn.loss_and_grad(rb, np.stack(imgs), sig, np.stack(tgts), round_act=bf16_round,
-                                              round_grad=bf16_round)
-    pr = np.random.default_rng(5)
+    w1, b1, mids, w17, b17 = dncnn.unpack(rb)
+    v = np.stack(imgs)
+    x0 = ocnn.network_input(v, sig)
+    worst = 0.0
 
-    def perturbed(x):
-        return bf16_round(x * (1 + 1e-6 * pr.standard_normal(np.shape(x))))
+    def check(stored_v, want, bound, what):
+        nonlocal worst
+        r = float(np.max(np.abs(stored_v - want) / bound))
+        worst = max(worst, r)
+        assert r <= 1.0, (what, r)
 
-    _, g_floor, _ = dncnn.loss_and_grad(rb, np.stack(imgs), sig, np.stack(tgts), round_act=perturbed,
-                                        round_grad=perturbed)
-    assert abs(got["loss"][0] - l_ref) < 1e-2 * l_ref, (got["loss"][0], l_ref)
+    want = bf16_round(np.maximum(ocnn.conv3x3(x0, w1, b1), 0.0))
+    check(A[0], want, fwd_bound(want, x0, w1, b1), "a1")
+    cache = dncnn.cache_from_stored(x0, A, Z)
+    for m, (w, gam, bet) in enumerate(mids):
+        want = bf16_round(ocnn.conv3x3(A[m], w, np.zeros(64)))
+        check(Z[m], want, fwd_bound(want, A[m], w, np.zeros(64)), f"z{m + 2}")
+        want = bf16_round(np.maximum(gam * cache["zhat"][m] + bet, 0.0))
+        check(A[m + 1], want, FWD_REL * np.abs(want) + 1e-5 * (np.abs(gam * cache["zhat"][m]) + np.abs(bet)) + 1e-30,
+              f"a{m + 2}")
+    f = ocnn.conv3x3(A[15], w17, b17)[..., 0]
+    assert np.max(np.abs(outv - (v - 255.0 * f))) < 1e-3
+    loss, g_ref, stats = dncnn.backward(rb, cache, outv, np.stack(tgts))
+    assert abs(got["loss"][0] - loss) < 1e-5 * loss, (got["loss"][0], loss)
     w1o, b1o, mid0, w17o, b17o, total = dncnn.offsets()
     pieces = [("W1", 0, b1o), ("b1", b1o, mid0)]
     for m in range(15):
@@ -140,12 +175,12 @@ def test_dncnn_training_step_matches_oracle():
                    (f"beta{m + 2}", o + 36928, o + dncnn.MID_STRIDE)]
     pieces += [("W17", w17o, b17o), ("b17", b17o, total)]
     for name, a0, a1 in pieces:
-        b = g_ref[a0:a1]
-        rel = float(np.linalg.norm(got["grad"][a0:a1] - b) / (np.linalg.norm(b) + 1e-30))
-        floor = float(np.linalg.norm(g_floor[a0:a1] - b) / (np.linalg.norm(b) + 1e-30))
-        assert rel < 2.0 * floor + 0.05, (name, rel, floor)
+        emax, el2 = group_errors(got["grad"][a0:a1], g_ref[a0:a1])
+        print(f"dncnn grad {name}: max {emax:.2e} l2 {el2:.2e}")
+        assert emax < GRAD_MAX and el2 < GRAD_L2, (name, emax, el2)
+    print(f"dncnn forward: worst {worst:.3f} of the bound")
     run_ref = dncnn.update_running(dncnn.init_running(), stats)
-    assert np.allclose(got["run"], run_ref, rtol=1e-3, atol=1e-4)
+    assert np.allclose(got["run"], run_ref, rtol=1e-5, atol=1e-6)
 
 
 def test_dncnn_adam_and_loss_decrease():
@@ -184,7 +219,8 @@ def test_ida_with_dncnn_denoiser_runs():
     img = synth.synth_image(230, 64, 64)
     px, d = pack_images([img])
     run = Run(px, [dict(d[0], block=16, subrate=0.25, method="dd")]).budget().sense()
-    prm = torch.from_numpy(np.concatenate([_blob(27), dncnn.init_running()]).astype(np.float32)).to(device())
+    prm = torch.from_numpy(g.denoiser_params(np.concatenate([_blob(27), dncnn.init_running()]), (0.5, 300.0))).to(
+        device())
     ws = torch.empty(g.ida_workspace_bytes(run.plan, "dncnn"), dtype=torch.uint8, device=device())
     x = torch.empty(run.plan.pixels, dtype=torch.float32, device=device())
     g.ida_refine(run.plan, run.y, run.k, run.off, x, 3, 2.0, "dncnn", params=prm, workspace=ws)
