@@ -229,6 +229,24 @@ int ida_refine(const abcs_plan* plan, const float* d_y, const int32_t* d_k, cons
                int iters, double damping, int denoiser, const void* d_params, float* d_x,
                float* d_sigma_trace, void* d_ws, size_t ws_bytes, void* stream);
 
+/* ida_refine for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same loop and results, with its workspace taken from a fixed scratch array
+ * that the library holds on each device it runs on (ida_noalloc_scratch_bytes()
+ * = 64 MiB per device, held until the process ends) instead of d_ws.  The
+ * call allocates nothing and copies nothing from the host; the caller still
+ * owns y, k, offsets, x and the trace.  Every call on a device shares that
+ * device's scratch, which keeps the last call's contents (the loop
+ * initialises everything it reads), so calls that overlap on one device race:
+ * serialise them (one stream, or events).
+ * Errors: those of ida_refine, and ENOSPACE when ida_workspace_bytes(plan,
+ * denoiser) exceeds the scratch (the CNN needs about 260 bytes per pixel,
+ * BM3D about 44, the identity about 8 plus 12 per coefficient). */
+size_t ida_noalloc_scratch_bytes(void);
+int ida_refine_noalloc(const abcs_plan* plan, const float* d_y, const int32_t* d_k, const int64_t* d_offsets,
+                       int iters, double damping, int denoiser, const void* d_params, float* d_x,
+                       float* d_sigma_trace, void* stream);
+
 /* The signed BBV samples (Section V-A: the encoder measures them for eq 19
  * and may send them as extra reconstruction measurements): each is
  * d = I[a] - I[b] for two adjacent pixels on a block border, a the later one

@@ -14,4 +14,4 @@ from .api import (ZZ, BBV, DD, Plan, AbcsError, budget, sense, reconstruct,  # n
                   threshold_workspace_bytes, budget_correlation, RULES, TRANSFORMS,
                   bbv_samples, ida_refine_bbv, dncnn_param_count, dncnn_running_count,
                   dncnn_train_workspace_bytes, dncnn_train_step, workspace_part,
-                  denoiser_params)
+                  ida_refine_noalloc, ida_noalloc_scratch_bytes, denoiser_params)

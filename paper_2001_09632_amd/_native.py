@@ -18,6 +18,7 @@ EXPORTS = [
     "abcs_bbv_samples", "ida_refine_bbv",
     "abcs_dncnn_param_count", "abcs_dncnn_running_count", "abcs_dncnn_train_workspace_bytes",
     "abcs_dncnn_train_step", "abcs_workspace_part",
+    "ida_noalloc_scratch_bytes", "ida_refine_noalloc",
 ]
 
 
@@ -98,6 +99,9 @@ def lib():
     L.abcs_dncnn_train_workspace_bytes.argtypes = [vp]
     L.abcs_dncnn_train_workspace_bytes.restype = sz
     L.abcs_dncnn_train_step.argtypes = [vp, vp, vp, vp, vp, i64, ctypes.c_float, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.ida_noalloc_scratch_bytes.argtypes = []
+    L.ida_noalloc_scratch_bytes.restype = sz
+    L.ida_refine_noalloc.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp]
     L.abcs_workspace_part.argtypes = [vp, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     L.ida_graph_destroy.argtypes = [vp]
     L.ida_graph_destroy.restype = None
@@ -107,7 +111,7 @@ def lib():
                         "amp_workspace_bytes", "abcs_threshold_workspace_bytes",
                         "abcs_dncnn_param_count", "abcs_dncnn_running_count", "abcs_dncnn_train_workspace_bytes",
                         "abcs_denoise_workspace_bytes", "abcs_cnn_param_count",
-                        "abcs_cnn_train_workspace_bytes"):
+                        "abcs_cnn_train_workspace_bytes", "ida_noalloc_scratch_bytes"):
             f.restype = ctypes.c_int
     _lib = L
     return L

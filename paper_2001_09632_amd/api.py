@@ -125,6 +125,19 @@ def ida_refine(plan, y, k, offsets, x, iters, damping=2.0, denoiser="identity", 
                            _stream(stream)))
 
 
+def ida_noalloc_scratch_bytes():
+    return int(lib().ida_noalloc_scratch_bytes())
+
+
+def ida_refine_noalloc(plan, y, k, offsets, x, iters, damping=2.0, denoiser="identity", params=None,
+                       sigma_trace=None, stream=None):
+    """ida_refine_noalloc: ida_refine with the library's fixed per-device
+    scratch in place of a workspace (no allocation)."""
+    d = DENOISERS[denoiser] if isinstance(denoiser, str) else int(denoiser)
+    check(lib().ida_refine_noalloc(plan.handle, _ptr(y), _ptr(k), _ptr(offsets), int(iters), float(damping), d,
+                                   _ptr(params), _ptr(x), _ptr(sigma_trace), _stream(stream)))
+
+
 def bbv_samples(plan, px, out, stream=None):
     """abcs_bbv_samples: out float32[plan.bbv_total] <- the signed BBV samples."""
     check(lib().abcs_bbv_samples(plan.handle, _ptr(px), px.numel() * px.element_size(), _ptr(out),
