@@ -4,13 +4,14 @@
 Workload (one step): a batch of 64 synthetic 512x512 uint8 greyscale images
 (seeds 1000..1063), B = 16, both budget estimators (AL-DCT-BBV and
 AL-DCT-DD) at subrates 0.1, 0.2, 0.3, 0.4, 0.5 - 640 image encodings in one
-plan - run through phase-1 statistics + budget apportionment (abcs_budget),
-phase-2 sensing (abcs_sense) and the masked inverse 2D-DCT decoder
-(abcs_reconstruct), float32.  Inputs are resident in HBM before timing starts.
+plan - run through phase-1 statistics + budget apportionment (abcs_budget)
+and phase-2 sensing with the masked inverse 2D-DCT decoder in one pass
+(abcs_sense_decode), float32: the two halves of abcs_encode.  Inputs are
+resident in HBM before timing starts.
 
 Prints one JSON line: Mpixel/s over the whole step, the roofline of the
-dominant kernel (HIP events on the launch stream) and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+dominant kernel (HIP events on the launch stream) and of the whole step,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -61,7 +62,45 @@ def algorithmic_bytes(plan, kind):
         return 4 * plan.meas + 12 * plan.blocks + 4 * plan.pixels
     if kind == "sense":
         return plan.pixels + 12 * plan.blocks + 4 * plan.meas
+    if kind == "sense_decode":
+        return plan.pixels + 12 * plan.blocks + 4 * plan.meas + 4 * plan.pixels
     raise ValueError(kind)
+
+
+def oracle_decodes(images, plan, k_all, n_images=8):
+    """The float64 oracle's decoding of its own measurements for the first
+    n_images at every (estimator, subrate) pair: {plan image index: image}.
+    The budgets are the GPU's, which equal the oracle's bit for bit (checked
+    here as well)."""
+    from oracle import abcs as orc
+    out = {}
+    for j, d in enumerate(plan.images):
+        i = j % len(SEEDS)
+        if i >= n_images:
+            continue
+        m = METHODS[j // (len(SEEDS) * len(SUBRATES))]
+        cr = SUBRATES[(j // len(SEEDS)) % len(SUBRATES)]
+        k, _ = orc.budget(images[i], B, cr, orc.METHOD_NAMES[m])
+        b0 = d["block_offset"]
+        assert (k_all[b0:b0 + k.size] == k).all(), "budget differs from the oracle"
+        out[j] = orc.reconstruct(orc.sense(images[i], B, k), B, k, H, W)
+    return out
+
+
+def precision_errors(plan, out_host, sample, images):
+    """Largest |pixel - oracle pixel| and mean |dPSNR| (clean image as
+    reference) over the sampled encodings."""
+    import numpy as np
+    from oracle import metrics
+    mx, dp = 0.0, []
+    for j, ref in sample.items():
+        d = plan.images[j]
+        got = out_host[d["out_offset"]:d["out_offset"] + H * W].reshape(H, W).astype(np.float64)
+        mx = max(mx, float(np.max(np.abs(got - ref))))
+        clean = images[j % len(SEEDS)].astype(np.float64)
+        dp.append(abs(metrics.psnr(got, clean) - metrics.psnr(ref, clean)))
+    return {"max_abs_dpx_vs_oracle": round(mx, 6), "mean_abs_dpsnr_vs_oracle_db": round(float(np.mean(dp)), 6),
+            "max_abs_dpsnr_vs_oracle_db": round(float(np.max(dp)), 6), "sampled_encodings": len(sample)}
 
 
 # HBM traffic of a kernel on this workload: rocprofv3 --pmc FETCH_SIZE and
@@ -289,6 +328,44 @@ STREAM_SIZES = [(256, 256), (512, 512), (768, 1024), (2048, 2048)]   # (H, W); 1
 STREAM_BUDGET_BYTES = 1 << 30   # device bytes of y + decoded images admitted per batch
 
 
+def single_image_section(dev, reps=200):
+    """One 256x256 synthetic image (seed 0), B = 16, AL-DCT-BBV at C_R 0.25,
+    float32: abcs_encode (budget, sensing and the decoder's image) per call,
+    latency-bound at this size; budgets checked against the oracle and the
+    decoded pixels against the oracle's decoding of its own float64
+    measurements."""
+    import numpy as np
+    import torch
+    import paper_2001_09632_amd as g
+    import synth
+    from oracle import abcs as orc
+    img = synth.synth_image(0, 256, 256)
+    px = torch.from_numpy(img.reshape(-1)).to(dev)
+    plan = g.Plan([dict(height=256, width=256, row_pitch=256, block=16, subrate=0.25, method="bbv",
+                        pixel_offset=0)])
+    k = torch.empty(plan.blocks, dtype=torch.int32, device=dev)
+    off = torch.empty(plan.blocks, dtype=torch.int64, device=dev)
+    st = torch.empty(plan.blocks, dtype=torch.int32, device=dev)
+    y = torch.empty(plan.meas, dtype=torch.float32, device=dev)
+    out = torch.empty(plan.pixels, dtype=torch.float32, device=dev)
+    for _ in range(10):
+        g.encode(plan, px, k, off, st, y, out)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record()
+    for _ in range(reps):
+        g.encode(plan, px, k, off, st, y, out)
+    e[1].record()
+    torch.cuda.synchronize()
+    ms = e[0].elapsed_time(e[1]) / reps
+    kk, _, yy = orc.encode(img, 16, 0.25, orc.BBV)
+    ref = orc.reconstruct(yy, 16, kk, 256, 256)
+    return {"workload": "one 256x256 synthetic image (seed 0), B=16, AL-DCT-BBV, C_R 0.25, float32, abcs_encode",
+            "ms_per_image": round(ms, 4), "mpixel_per_s": round(65536 / ms / 1e3, 1),
+            "budgets_equal_oracle": bool(np.array_equal(k.cpu().numpy(), kk)),
+            "max_abs_dpx_vs_oracle": round(float(np.max(np.abs(out.cpu().numpy().reshape(256, 256) - ref))), 6)}
+
+
 def stream_requests(n, seed=5):
     """n requests of the mixed stream: size uniform over STREAM_SIZES, B over
     {8, 16, 32}, C_R ~ U(0.05, 0.5), budget rule over {ZZ, BBV, DD}."""
@@ -301,9 +378,10 @@ def stream_requests(n, seed=5):
 
 def stream_section(dev, n_requests=1000, load=0.5):
     """The mixed request stream: every request is encoded (budget + sense) and
-    decoded (masked inverse DCT) on the GPU.  Requests are batched in arrival
-    order while their y and decoded images fit STREAM_BUDGET_BYTES; one plan
-    per batch (its creation is part of the timed work).  Image content comes
+    decoded (masked inverse DCT) on the GPU with abcs_encode.  Requests are
+    batched in arrival order while their y and decoded images fit
+    STREAM_BUDGET_BYTES; one plan per batch (host work: timed apart from the
+    GPU work in the saturated run, inside the latency in the stream).  Image content comes
     from a pool of one synthetic image per size held in device memory.  First
     all requests arrive at once (saturated Mpixel/s), then as a Poisson stream
     (seed 7) at `load` times the saturated pixel rate; latency = completion -
@@ -351,21 +429,35 @@ def stream_section(dev, n_requests=1000, load=0.5):
     yb = torch.empty(STREAM_BUDGET_BYTES // 4, dtype=torch.float32, device=dev)
     xb = torch.empty(STREAM_BUDGET_BYTES // 4, dtype=torch.float32, device=dev)
 
-    def run_batch(idx):
-        plan = g.Plan([entry(reqs[i]) for i in idx])
-        g.budget(plan, px, kb, ob, sb)
-        g.sense(plan, px, kb, ob, yb)
-        g.reconstruct(plan, yb, kb, ob, xb)
+    plan_s = []
+
+    def make_plan(idx):
+        t = time.perf_counter()
+        plan = g.Plan([entry(reqs[i]) for i in idx], features=())
+        plan_s.append(time.perf_counter() - t)
+        return plan
+
+    def run_plan(plan):
+        g.encode(plan, px, kb, ob, sb, yb, xb)
         torch.cuda.synchronize()
         return plan.pixels
 
-    run_batch(list(range(min(8, n_requests))))          # warm up
+    run_plan(make_plan(list(range(min(8, n_requests)))))          # warm up
+    # saturated: every request at once; the batches' plans are made first
+    # (host work, timed on its own), then the GPU runs them back to back
+    plan_s.clear()
+    plans = [make_plan(b) for b in batches(range(n_requests))]
+    plan_total_s = sum(plan_s)
     t0 = time.perf_counter()
     total_px = 0
-    for b in batches(range(n_requests)):
-        total_px += run_batch(b)
+    for plan in plans:
+        total_px += run_plan(plan)
     sat_s = time.perf_counter() - t0
     sat_rate = total_px / sat_s
+    del plans
+
+    def run_batch(idx):
+        return run_plan(make_plan(idx))
 
     # Poisson arrivals at `load` of the saturated pixel rate
     rng = np.random.default_rng(7)
@@ -387,14 +479,18 @@ def stream_section(dev, n_requests=1000, load=0.5):
         nxt = batch[-1] + 1
     span = done.max()
     lat = (done - arrive) * 1e3
+    n_sat = len(batches(range(n_requests)))
+    stream_plans = plan_s[n_sat:]
     return {"workload": f"{n_requests} requests: 256x256 / 512x512 / 1024x768 / 2048x2048 uniform, B 8/16/32, "
-                        "C_R ~ U(0.05,0.5), ZZ/BBV/DD; budget+sense+inverse DCT, plan per batch",
+                        "C_R ~ U(0.05,0.5), ZZ/BBV/DD; abcs_encode (budget+sense+inverse DCT), plan per batch",
             "pixels": int(total_px), "batch_budget_bytes": STREAM_BUDGET_BYTES,
             "saturated": {"mpixel_per_s": round(sat_rate / 1e6, 1), "seconds": round(sat_s, 4),
-                          "batches": len(batches(range(n_requests)))},
+                          "batches": n_sat, "plan_seconds": round(plan_total_s, 4),
+                          "mpixel_per_s_with_planning": round(total_px / (sat_s + plan_total_s) / 1e6, 1)},
             "stream": {"offered_load": load, "mpixel_per_s": round(total_px / span / 1e6, 1),
                        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
-                                      "p99": round(float(np.percentile(lat, 99)), 3)}}}
+                                      "p99": round(float(np.percentile(lat, 99)), 3)},
+                       "plan_ms_mean": round(1e3 * float(np.mean(stream_plans)), 3) if stream_plans else None}}
 
 
 def bounds_section(dev, plan, px, k, out, images):
@@ -542,26 +638,50 @@ def train_section(dev, batch=32, steps=10):
     return out
 
 
-def cpu_baseline(images, n_images, deadline_s=30.0):
-    """The FP64 oracle (budget + sensing + decoding) on the first n_images of
-    the batch at every (estimator, subrate) pair; single-threaded numpy."""
+def _oracle_encodings(img):
+    """Budget + sensing + decoding of one image at every (estimator, subrate)
+    pair by the FP64 oracle, with numpy's BLAS held to one thread; returns
+    the pixels encoded."""
+    from threadpoolctl import threadpool_limits
     from oracle import abcs as orc
-    t0 = time.perf_counter()
-    done_px = 0
-    done = 0
-    for i in range(n_images):
+    with threadpool_limits(1):
         for m in METHODS:
             for cr in SUBRATES:
-                k, _, y = orc.encode(images[i], B, cr, orc.METHOD_NAMES[m])
+                k, _, y = orc.encode(img, B, cr, orc.METHOD_NAMES[m])
                 orc.reconstruct(y, B, k, H, W)
-                done_px += H * W
-                done += 1
-        if time.perf_counter() - t0 > deadline_s:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=done_px / dt / 1e6, unit="Mpixel/s", cores=1, kind="oracle",
-                sample=f"{done} of 640 image encodings (first {done // 10} images x 2 estimators x 5 subrates), "
-                       f"budget+sense+inverse DCT in float64 numpy, {dt:.1f} s")
+    return len(METHODS) * len(SUBRATES) * img.size
+
+
+def _pool_ready(_):
+    import oracle.abcs  # noqa: F401
+    import threadpoolctl  # noqa: F401
+    return os.getpid()
+
+
+def cpu_baseline(images, single_s=10.0):
+    """The FP64 oracle (budget + sensing + decoding, numpy) on the host's
+    cores: one worker process per core of this process's CPU set, each image's
+    ten encodings in one worker, over all 64 images (workers started before
+    the clock); and one thread alone on the first images for about
+    `single_s` seconds."""
+    from concurrent.futures import ProcessPoolExecutor
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    px1, n1 = 0, 0
+    while n1 < len(images) and time.perf_counter() - t0 < single_s:
+        px1 += _oracle_encodings(images[n1])
+        n1 += 1
+    dt1 = time.perf_counter() - t0
+    with ProcessPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(_pool_ready, range(cores)))
+        t0 = time.perf_counter()
+        pxn = sum(ex.map(_oracle_encodings, list(images)))
+        dtn = time.perf_counter() - t0
+    return dict(value=pxn / dtn / 1e6, unit="Mpixel/s", cores=cores, kind="oracle",
+                sample=f"all 640 image encodings (64 images x 2 estimators x 5 subrates), budget+sense+inverse DCT "
+                       f"in float64 numpy, one worker process per core, {dtn:.1f} s",
+                single_thread={"value": round(px1 / dt1 / 1e6, 3), "unit": "Mpixel/s",
+                               "sample": f"{10 * n1} encodings ({n1} images), {dt1:.1f} s"})
 
 
 def main():
@@ -569,7 +689,6 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-images", type=int, default=48)
     ap.add_argument("--no-stream", action="store_true", help="skip the mixed request-stream section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ida", action="store_true")
@@ -636,23 +755,23 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
+        # abcs_encode's two halves, so that each launch can be timed:
+        # phase-1 statistics + apportionment, then sensing and the decoder in
+        # one pass over each tile
         if ev is not None:
             ev[0].record(stream)
         g.budget(plan, px, k, off, stat, stream)
         if ev is not None:
             ev[1].record(stream)
-        g.sense(plan, px, k, off, y, stream)
+        g.sense_decode(plan, px, k, off, y, out, stream)
         if ev is not None:
             ev[2].record(stream)
-        g.reconstruct(plan, y, k, off, out, stream)
-        if ev is not None:
-            ev[3].record(stream)
 
     log("warmup")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     log("timing")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -661,43 +780,70 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_budget = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    ms_sense = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    ms_recon = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    ms_sd = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ms_step = elapsed / args.steps * 1e3
 
     pixels_per_step = plan.pixels
     value = pixels_per_step * args.steps / elapsed / 1e6
-    kernels = {"sense": ms_sense, "reconstruct": ms_recon}
-    dom = max(kernels, key=kernels.get)
-    ach = algorithmic_bytes(plan, dom) / (kernels[dom] * 1e-3) / 1e9
-    roofline = dict(bound="hbm", kernel=dom, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=measured_traffic(dom),
-                    algorithmic_bytes=algorithmic_bytes(plan, dom))
-    per_kernel_ms = dict(budget=round(ms_budget, 4), sense=round(ms_sense, 4), reconstruct=round(ms_recon, 4))
+    # the dominant launch: sensing + decoding (k_encode16); it moves every
+    # byte the step must move (pixels in, y and the decoded images out, k
+    # and offsets in), so its algorithmic bytes are the step's as well
+    step_bytes = algorithmic_bytes(plan, "sense_decode")
+    ach = step_bytes / (ms_sd * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel="sense_decode (k_encode16)", achieved=round(ach, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=measured_traffic("sense_decode"),
+                    algorithmic_bytes=step_bytes)
+    ach_step = step_bytes / (ms_step * 1e-3) / 1e9
+    roofline_step = dict(bound="hbm", achieved=round(ach_step, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(ach_step / HBM_PEAK_GBS, 4), algorithmic_bytes=step_bytes,
+                         basis="(1 + 4 y/pixel + 4 + 12/B^2) bytes per pixel over ms_per_step")
+    per_kernel_ms = dict(budget=round(ms_budget, 4), sense_decode=round(ms_sd, 4))
 
-    # The 16-bit operand modes of the same two transforms (budget unchanged):
-    # time per call, and the largest deviation of y and of the decoded images
-    # from the float32 path.  Context only; the headline is float32.
-    prec = {}
+    # The same step as three calls (budget, sense, reconstruct: the decoder
+    # reads y back), for comparison.
     y32, out32 = y.clone(), out.clone()
+    e3 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for rep in range(2):
+        e3[0].record(stream)
+        for _ in range(10):
+            g.sense(plan, px, k, off, y, stream)
+        e3[1].record(stream)
+        for _ in range(10):
+            g.reconstruct(plan, y, k, off, out, stream)
+        e3[2].record(stream)
+        torch.cuda.synchronize()
+    per_kernel_ms["sense_alone"] = round(e3[0].elapsed_time(e3[1]) / 10, 4)
+    per_kernel_ms["reconstruct_alone"] = round(e3[1].elapsed_time(e3[2]) / 10, 4)
+    assert torch.equal(y, y32) and torch.equal(out, out32), "separate calls differ from the fused pass"
+
+    # The 16-bit operand modes of the same transforms (budget unchanged):
+    # time per sense_decode call, and the deviation of y and of the decoded
+    # images from the float32 path and from the float64 oracle (on a sample
+    # of 8 images at every estimator and subrate).  Context only; the
+    # headline is float32.
+    prec = {}
     y_m = torch.empty_like(y)
     out_m = torch.empty_like(out)
+    sample = oracle_decodes(images, plan, k.cpu().numpy())
+    prec["fp32"] = precision_errors(plan, out32.cpu().numpy(), sample, images)
+    prec["fp32"]["sense_decode_ms"] = round(ms_sd, 4)
     for mode in ("bf16x3", "fp16x3", "bf16", "fp16"):
-        g.sense(plan, px, k, off, y_m, stream, precision=mode)
-        g.reconstruct(plan, y_m, k, off, out_m, stream, precision=mode)
+        g.sense_decode(plan, px, k, off, y_m, out_m, stream, precision=mode)
         torch.cuda.synchronize()
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         e[0].record(stream)
         for _ in range(5):
-            g.sense(plan, px, k, off, y_m, stream, precision=mode)
+            g.sense_decode(plan, px, k, off, y_m, out_m, stream, precision=mode)
         e[1].record(stream)
-        for _ in range(5):
-            g.reconstruct(plan, y_m, k, off, out_m, stream, precision=mode)
-        e[2].record(stream)
         torch.cuda.synchronize()
-        prec[mode] = {"sense_ms": round(e[0].elapsed_time(e[1]) / 5, 4),
-                      "reconstruct_ms": round(e[1].elapsed_time(e[2]) / 5, 4),
+        rec_m = precision_errors(plan, out_m.cpu().numpy(), sample, images)
+        rec_m.update({"sense_decode_ms": round(e[0].elapsed_time(e[1]) / 5, 4),
                       "max_abs_dy_vs_fp32": round(float((y_m - y32).abs().max()), 5),
-                      "max_abs_dpx_vs_fp32": round(float((out_m - out32).abs().max()), 5)}
+                      "max_abs_dpx_vs_fp32": round(float((out_m - out32).abs().max()), 5)})
+        prec[mode] = rec_m
+
+    log("single image")
+    single = single_image_section(dev)
 
     bounds = None
     if not args.no_bounds:
@@ -727,7 +873,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        cpu = cpu_baseline(images, args.cpu_images)
+        cpu = cpu_baseline(images)
 
     rec = {
         "metric": "Mpixel/s ABCS sense+iDCT; IDA images/s at matched PSNR, learned vs plain",
@@ -736,19 +882,22 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "64 synthetic 512x512 uint8 images, B=16, AL-DCT-BBV and AL-DCT-DD at C_R "
-                               "0.1/0.2/0.3/0.4/0.5 (640 encodings per step): budget + sense + masked inverse DCT",
+                               "0.1/0.2/0.3/0.4/0.5 (640 encodings per step): budget + sense + masked inverse DCT "
+                               "(abcs_budget, then abcs_sense_decode: 2 launches)",
                    "images": len(SEEDS), "height": H, "width": W, "block": B, "encodings_per_step": plan.n,
                    "pixels_per_step": pixels_per_step},
         "per_kernel_ms": per_kernel_ms,
         "precision_modes": prec,
+        "single_image": single,
         "roofline": roofline,
+        "roofline_step": roofline_step,
         "cpu_baseline": cpu,
         "bounds": bounds,
         "wht": wht,

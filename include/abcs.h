@@ -148,6 +148,18 @@ typedef struct abcs_plan abcs_plan; /* opaque */
  * on the vector ALUs (same results and error bars for every B: budgets and
  * index sets exact, DD statistics evaluated in float64). */
 int abcs_plan_create(const abcs_image* h_imgs, int n, abcs_plan** out);
+/* abcs_plan_create with a choice of tables: the tables of the encoder and the
+ * decoder (budget, sense, reconstruct, encode, the identity-denoiser IDA
+ * loop, BBV samples, correlation) are always built; ABCS_PLAN_DENOISE adds
+ * those of the denoisers (BM3D reference grids, CNN tiles, the per-64-pixel
+ * image map: needed by every non-identity denoiser, amp_refine and the
+ * training steps) and ABCS_PLAN_BOUNDS those of abcs_threshold.  A call that
+ * needs a table the plan lacks returns EINVAL.  abcs_plan_create builds all
+ * of them; a stream of encode-only batches saves their host work and device
+ * memory (about 1 + 12 / B^2 bytes per pixel for the bounds' tables, and
+ * most of the plan's creation time for large batches). */
+typedef enum abcs_plan_feature { ABCS_PLAN_DENOISE = 1, ABCS_PLAN_BOUNDS = 2 } abcs_plan_feature;
+int abcs_plan_create_ex(const abcs_image* h_imgs, int n, unsigned features, abcs_plan** out);
 void abcs_plan_destroy(abcs_plan* plan);
 
 /* Totals of a plan: number of blocks (length of k, offsets, stat), number of
@@ -193,6 +205,23 @@ int abcs_sense(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes,
  * d_out: out, float[pixels], each image H' x W' with row pitch W'. */
 int abcs_reconstruct(const abcs_plan* plan, const float* d_y, const int32_t* d_k,
                      const int64_t* d_offsets, float* d_out, int precision, void* stream);
+
+/* The whole encoder of Algorithms 1 and 2 in one call, with the decoder's
+ * image alongside: abcs_budget (phase-1 statistics, apportionment, offsets),
+ * then abcs_sense, then, when d_out is not NULL, the image abcs_reconstruct
+ * would decode from the same y (an encoder's local decoder, as in the
+ * real-time system of Fig 1).  For float32 16 x 16 images sensing and
+ * decoding are one pass over each tile: the decoder takes the coefficients
+ * from the forward transform instead of reading y back, with the same
+ * arithmetic as abcs_reconstruct, so d_out equals abcs_reconstruct's output
+ * bit for bit.  Arguments and errors as the three calls; d_out nullable,
+ * float[pixels], 16-byte aligned. */
+int abcs_encode(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, int32_t* d_k,
+                int64_t* d_offsets, int32_t* d_stat, float* d_y, float* d_out, int precision, void* stream);
+/* The second half of abcs_encode on its own (budgets already in d_k and
+ * d_offsets): abcs_sense and the decoder's image in d_out (not NULL). */
+int abcs_sense_decode(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, const int32_t* d_k,
+                      const int64_t* d_offsets, float* d_y, float* d_out, int precision, void* stream);
 
 /* IDA post-processing (Section VI; eqs 13, 15, 25, 28; Fig 6).
  * Starting from x^0 = 0 and z^{-1} = 0, iteration t = 0 .. iters-1 computes

@@ -9,7 +9,7 @@ ABCS_OK, ABCS_EINVAL, ABCS_EDOMAIN, ABCS_EUNSUPPORTED, ABCS_ENOSPACE, ABCS_EHIP 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EDOMAIN", -3: "EUNSUPPORTED", -4: "ENOSPACE", -5: "EHIP"}
 
 EXPORTS = [
-    "abcs_plan_create", "abcs_plan_destroy", "abcs_plan_totals", "abcs_plan_image",
+    "abcs_plan_create", "abcs_plan_create_ex", "abcs_plan_destroy", "abcs_plan_totals", "abcs_plan_image",
     "abcs_budget", "abcs_sense", "abcs_reconstruct", "abcs_dct_basis", "abcs_last_error",
     "ida_workspace_bytes", "ida_refine", "ida_iterate", "abcs_denoise_workspace_bytes", "abcs_denoise",
     "abcs_cnn_param_count", "abcs_cnn_train_workspace_bytes", "abcs_cnn_train_step",
@@ -17,7 +17,7 @@ EXPORTS = [
     "abcs_threshold_workspace_bytes", "abcs_threshold", "abcs_budget_correlation",
     "abcs_bbv_samples", "ida_refine_bbv",
     "abcs_dncnn_param_count", "abcs_dncnn_running_count", "abcs_dncnn_train_workspace_bytes",
-    "abcs_dncnn_train_step", "abcs_workspace_part",
+    "abcs_dncnn_train_step", "abcs_workspace_part", "abcs_encode", "abcs_sense_decode",
     "ida_noalloc_scratch_bytes", "ida_refine_noalloc",
 ]
 
@@ -59,6 +59,7 @@ def lib():
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
     P64 = ctypes.POINTER(ctypes.c_int64)
     L.abcs_plan_create.argtypes = [ctypes.POINTER(ImageDesc), i32, ctypes.POINTER(vp)]
+    L.abcs_plan_create_ex.argtypes = [ctypes.POINTER(ImageDesc), i32, ctypes.c_uint, ctypes.POINTER(vp)]
     L.abcs_plan_destroy.argtypes = [vp]
     L.abcs_plan_destroy.restype = None
     L.abcs_plan_totals.argtypes = [vp, P64, P64, P64]
@@ -66,6 +67,8 @@ def lib():
     L.abcs_budget.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.abcs_sense.argtypes = [vp, vp, i64, vp, vp, vp, i32, vp]
     L.abcs_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, vp]
+    L.abcs_encode.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, i32, vp]
+    L.abcs_sense_decode.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, vp]
     L.abcs_dct_basis.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
     L.abcs_last_error.restype = ctypes.c_char_p
     L.ida_workspace_bytes.argtypes = [vp, i32]

@@ -28,10 +28,14 @@ class Plan:
     method (0/1/2 or 'zz'/'bbv'/'dd'), and optionally transform ('dct'
     (default) or 'wht', or 0/1), row_pitch (default width rounded up to 4)
     and pixel_offset (default: images packed one after the other).  Create it
-    with the target device current.
+    with the target device current.  `features` names the optional tables to
+    build ('denoise': every non-identity denoiser, D-AMP and training;
+    'bounds': THI / THB); an encoder/decoder-only plan passes ().
     """
 
-    def __init__(self, images):
+    FEATURES = {"denoise": 1, "bounds": 2}
+
+    def __init__(self, images, features=("denoise", "bounds")):
         imgs = list(images)
         arr = (ImageDesc * max(1, len(imgs)))()
         offset = 0
@@ -50,7 +54,10 @@ class Plan:
             arr[i].transform = TRANSFORMS[xf] if isinstance(xf, str) else int(xf)
             arr[i].pixel_offset = int(po)
         self._h = ctypes.c_void_p()
-        check(lib().abcs_plan_create(arr, len(imgs), ctypes.byref(self._h)))
+        flags = 0
+        for f in features:
+            flags |= self.FEATURES[f]
+        check(lib().abcs_plan_create_ex(arr, len(imgs), flags, ctypes.byref(self._h)))
         self.n = len(imgs)
         b, m, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         check(lib().abcs_plan_totals(self._h, ctypes.byref(b), ctypes.byref(m), ctypes.byref(p)))
@@ -107,6 +114,19 @@ def reconstruct(plan, y, k, offsets, out, stream=None, precision="fp32"):
 
 IDENTITY, BM3D, CNN, DNCNN = 0, 1, 2, 3
 DENOISERS = {"identity": IDENTITY, "bm3d": BM3D, "cnn": CNN, "dncnn": DNCNN}
+
+
+def encode(plan, px, k, offsets, stat, y, out=None, stream=None, precision="fp32"):
+    """abcs_encode: budget + sense (+ the decoder's image into out, float32
+    [pixels], when given) in one call."""
+    check(lib().abcs_encode(plan.handle, _ptr(px), px.numel() * px.element_size(), _ptr(k), _ptr(offsets),
+                            _ptr(stat), _ptr(y), _ptr(out), _prec(precision), _stream(stream)))
+
+
+def sense_decode(plan, px, k, offsets, y, out, stream=None, precision="fp32"):
+    """abcs_sense_decode: sensing and the decoder's image (budgets given)."""
+    check(lib().abcs_sense_decode(plan.handle, _ptr(px), px.numel() * px.element_size(), _ptr(k), _ptr(offsets),
+                                  _ptr(y), _ptr(out), _prec(precision), _stream(stream)))
 
 
 def ida_workspace_bytes(plan, denoiser):

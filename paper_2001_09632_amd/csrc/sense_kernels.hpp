@@ -68,6 +68,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
 #pragma unroll
       for (int r = 0; r < 4; ++r) buf[h][L.zr[r]] = C[h][r];
     wave_lds_sync();
+    float yv[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yv[h][q] = buf[h][lane + 64 * q];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int kk = __builtin_amdgcn_readlane(io.k, b0 + h);
@@ -77,7 +82,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
         if (64 * q < kk) {
           const int z = lane + 64 * q;
           const uint32_t voff = z < kk ? rel4 + 4u * (uint32_t)z : 0xffffffffu;
-          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(buf[h][z]), io.y, voff, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(yv[h][q]), io.y, voff, 0, 0);
         }
       }
     }
@@ -119,6 +124,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
   lane16_init<XF>(L);
   Lane16P<P> H;
   if (P != kPrecFP32) lane16p_init(H, L);
+  Lane16T T;
+  if (P == kPrecFP32) lane16t_init<XF>(T, L);
   TileIO io;
   tile_io_init(io, im, tl, nullptr, y, k_all, off_all, L);
   const int lane = threadIdx.x & 63;
@@ -140,8 +147,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
 #pragma unroll
   for (int b = 0; b < kTileBlocks; b += 2) {
     // coefficients of this lane's quad that lie past the block's k
-    const int ka = __builtin_amdgcn_readlane(io.k, b) - 4 * lane;
-    const int kb = __builtin_amdgcn_readlane(io.k, b + 1) - 4 * lane;
+    const int kA = __builtin_amdgcn_readlane(io.k, b);
+    const int kB = __builtin_amdgcn_readlane(io.k, b + 1);
+    const int ka = kA - 4 * lane;
+    const int kb = kB - 4 * lane;
     u32x4 va = v[b], vb = v[b + 1];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -154,12 +163,17 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
     float e0[4], e1[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      e0[c] = buf0[L.zr[c]];
-      e1[c] = buf1[L.zr[c]];
+      e0[c] = buf0[P == kPrecFP32 ? T.zp[c] : L.zr[c]];
+      e1[c] = buf1[P == kPrecFP32 ? T.zp[c] : L.zr[c]];
     }
     wave_lds_sync();
-    const f32x4 A = P == kPrecFP32 ? idct16_inv(e0, L) : idct16_inv_p<P>(e0, H);
-    const f32x4 Bv = P == kPrecFP32 ? idct16_inv(e1, L) : idct16_inv_p<P>(e1, H);
+    f32x4 A, Bv;
+    if (P == kPrecFP32) {
+      idct16_inv_trunc2(e0, e1, T, idct16_steps(kA > kB ? kA : kB), A, Bv);
+    } else {
+      A = idct16_inv_p<P>(e0, H);
+      Bv = idct16_inv_p<P>(e1, H);
+    }
     f32x4 S1, S2;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -175,6 +189,115 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
     const uint32_t v2 = keep ? o2 + 64u * b : 0xffffffffu;
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, S1), ro, v1, 0, kStoreNT);
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, S2), ro, v2, 0, kStoreNT);
+  }
+}
+
+// Sensing and the local decoder in one pass (float32): every block's forward
+// transform, its first k_i zigzag coefficients written to y as k_sense16
+// does, and the masked inverse of the same coefficients written to out as
+// k_reconstruct16 does.  The forward transform leaves its output in the
+// truncated inverse's input layout (dct16_fwd_s), so the decoder reads the
+// coefficients from registers (masked past k_i by zigzag rank); only y goes
+// through LDS, to leave in unit-stride runs.  Both transforms compute the
+// same bits as k_sense16<kPrecFP32> and k_reconstruct16<kPrecFP32>.  The
+// forward products of the next pair of blocks are issued before the current
+// pair's stores and inverse, so that the matrix cores have work while the
+// wave waits on LDS and memory.
+template <int XF = kXfDCT>
+__global__ __launch_bounds__(kGroupThreads) void k_encode16(const ImgDev* __restrict__ imgs,
+                                                           const Tile* __restrict__ tiles, int ntiles,
+                                                           const uint8_t* __restrict__ px,
+                                                           const int32_t* __restrict__ k_all,
+                                                           const int64_t* __restrict__ off_all,
+                                                           float* __restrict__ y, float* __restrict__ out) {
+  typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+  __shared__ WaveLds lds[kWavesPerGroup][2];
+  __shared__ PxStage stage[kWavesPerGroup];
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= ntiles) return;
+  const Tile tl = tiles[wave];
+  const ImgDev im = imgs[tl.img];
+  Lane16 L;
+  lane16_init<XF>(L);
+  Lane16T T;
+  lane16t_init<XF>(T, L);
+  Lane16S S;
+  lane16s_init<XF>(S, L);
+  TileIO io;
+  tile_io_init(io, im, tl, px, y, k_all, off_all, L);
+  float* buf[2] = {lds[wave_in_group()][0].c, lds[wave_in_group()][1].c};
+  uint32_t* st = stage[wave_in_group()].w;
+  const int lane = threadIdx.x & 63;
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(out + tl.out_base, 4 * (15 * im.Wc + 16 * tl.count));
+  const bool lo = L.n < 8;
+  const int row = lo ? L.n : L.n - 8;
+  const uint32_t o1 = 4u * (uint32_t)(row * im.Wc + (lo ? 0 : 16) + 4 * L.g);
+  const uint32_t o2 = o1 + 4u * 8u * (uint32_t)im.Wc;
+  stage_tile_px(io, im.pitch, tl.count, st);
+  wave_lds_sync();
+  auto forward = [&](int b) {
+    const uint32_t pw = staged_px(st, b, L);
+    float a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = (float)((pw >> (8 * c)) & 0xffu);
+    return dct16_fwd_s(a, S);
+  };
+  f32x4 C[2] = {forward(0), forward(1)};
+#pragma unroll
+  for (int b0 = 0; b0 < kTileBlocks; b0 += 2) {
+    f32x4 Cn[2] = {C[0], C[1]};
+    if (b0 + 2 < kTileBlocks) {
+      Cn[0] = forward(b0 + 2);
+      Cn[1] = forward(b0 + 3);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[h][T.zp[r]] = C[h][r];
+    wave_lds_sync();
+    // all of the pair's LDS reads first, one wait, then the stores
+    float yv[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yv[h][q] = buf[h][lane + 64 * q];
+    int kk[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      kk[h] = __builtin_amdgcn_readlane(io.k, b0 + h);
+      const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(io.rel_lo, b0 + h);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (64 * q < kk[h]) {
+          const int z = lane + 64 * q;
+          const uint32_t voff = z < kk[h] ? rel4 + 4u * (uint32_t)z : 0xffffffffu;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(yv[h][q]), io.y, voff, 0, 0);
+        }
+      }
+    }
+    wave_lds_sync();
+    float e[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) e[h][r] = T.zp[r] < kk[h] ? C[h][r] : 0.f;
+    f32x4 A, Bv;
+    idct16_inv_trunc2(e[0], e[1], T, idct16_steps(kk[0] > kk[1] ? kk[0] : kk[1]), A, Bv);
+    f32x4 S1, S2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float ra = row_ror8(A[r]);
+      const float rb = row_ror8(Bv[r]);
+      S1[r] = lo ? A[r] : rb;
+      S2[r] = lo ? ra : Bv[r];
+    }
+    const bool keep = lo ? (b0 < tl.count) : (b0 + 1 < tl.count);
+    const uint32_t v1 = keep ? o1 + 64u * b0 : 0xffffffffu;
+    const uint32_t v2 = keep ? o2 + 64u * b0 : 0xffffffffu;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, S1), ro, v1, 0, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, S2), ro, v2, 0, kStoreNT);
+    C[0] = Cn[0];
+    C[1] = Cn[1];
   }
 }
 

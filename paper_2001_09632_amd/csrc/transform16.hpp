@@ -88,6 +88,93 @@ __device__ __forceinline__ f32x4 idct16_inv(const float e[4], const Lane16& L) {
   return out;
 }
 
+// Inverse transform of zigzag-truncated blocks, skipping the products whose
+// operands are all zero.  The K slots of product c are the frequencies
+// 4c .. 4c+3 (instead of c, c+4, c+8, c+12 as in idct16_inv): lane l = 16g + n
+// supplies A = C[4c+g][s(n)] with s(n) = 4 (n % 4) + n / 4, so that the
+// first product's accumulator register c holds the rows Q[4c+g] of
+// Q = C^T D, which are then the K slots of the second product.  A block with
+// k coefficients has non-zero entries only on anti-diagonals u + v <= d,
+// d the diagonal of zigzag rank k - 1, so both products stop after
+// min(4, d / 4 + 1) steps: 1 step for k <= 10, 2 for k <= 36, 3 for k <= 78.
+// The skipped steps would add exact zeros, so the result does not depend on
+// where the chain stops.
+struct Lane16T {
+  float dP[4];  // D[4c+g][n]
+  int zp[4];    // zigzag rank of coefficient (4c+g, s(n))
+};
+
+template <int XF = kXfDCT>
+__device__ __forceinline__ void lane16t_init(Lane16T& T, const Lane16& L) {
+  const float* D = Basis16<XF>::D();
+  const int v = 4 * (L.n & 3) + (L.n >> 2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    T.dP[c] = D[(4 * c + L.g) * 16 + L.n];
+    T.zp[c] = c_zzrank16[(4 * c + L.g) * 16 + v];
+  }
+}
+
+// Forward transform with its output in the input layout of
+// idct16_inv_trunc2: register r of lane l = 16g + n receives C[4r+g][s(n)].
+// Both products take the basis rows in the order s: the first as
+// B = D[s(n)][4g+c] (so T's columns come out as frequencies s(n)), the second
+// as A = D[s(n)][4g+c] (so output row m is frequency s(m), and
+// s(4g + r) = 4r + g).  Only the rows and columns of the products move; every
+// output is summed over the same K slots in the same order as by dct16_fwd,
+// so the values are the same bits.
+struct Lane16S {
+  float dS[4];  // D[s(n)][4g+c]
+};
+
+template <int XF = kXfDCT>
+__device__ __forceinline__ void lane16s_init(Lane16S& S, const Lane16& L) {
+  const float* D = Basis16<XF>::D();
+  const int v = 4 * (L.n & 3) + (L.n >> 2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) S.dS[c] = D[v * 16 + 4 * L.g + c];
+}
+
+__device__ __forceinline__ f32x4 dct16_fwd_s(const float a[4], const Lane16S& S) {
+  f32x4 t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) t = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], S.dS[c], t, 0, 0, 0);
+  f32x4 out = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) out = __builtin_amdgcn_mfma_f32_16x16x4f32(S.dS[c], t[c], out, 0, 0, 0);
+  return out;
+}
+
+// Products per stage for a block whose first k zigzag coefficients may be
+// non-zero (diagonals 0-3 hold ranks 0-9, 0-7 ranks 0-35, 0-11 ranks 0-77).
+__device__ __forceinline__ int idct16_steps(int k) { return (k > 0) + (k > 10) + (k > 36) + (k > 78); }
+
+// Two blocks' truncated inverses with their product chains interleaved; in:
+// e[c] = C[4c+g][s(n)] (zero past each block's k), steps = idct16_steps of
+// the larger k (wave-uniform: the smaller block's extra products add exact
+// zeros); out X[n][4g+r] as idct16_inv.
+__device__ __forceinline__ void idct16_inv_trunc2(const float ea[4], const float eb[4], const Lane16T& T, int steps,
+                                                  f32x4& xa, f32x4& xb) {
+  f32x4 qa = {0.f, 0.f, 0.f, 0.f}, qb = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c < steps) {
+      qa = __builtin_amdgcn_mfma_f32_16x16x4f32(ea[c], T.dP[c], qa, 0, 0, 0);
+      qb = __builtin_amdgcn_mfma_f32_16x16x4f32(eb[c], T.dP[c], qb, 0, 0, 0);
+    }
+  }
+  xa = {0.f, 0.f, 0.f, 0.f};
+  xb = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c < steps) {
+      xa = __builtin_amdgcn_mfma_f32_16x16x4f32(T.dP[c], qa[c], xa, 0, 0, 0);
+      xb = __builtin_amdgcn_mfma_f32_16x16x4f32(T.dP[c], qb[c], xb, 0, 0, 0);
+    }
+  }
+}
+
+
 // ---------------------------------------------------------------------------
 // 16-bit operand modes of the same transforms (v_mfma_f32_16x16x16_f16 /
 // _bf16, float32 sums).  Lane l = 16g + n supplies A[n][4g .. 4g+3] and

@@ -55,6 +55,14 @@ class Run:
         g.reconstruct(self.plan, self.y if y is None else y, self.k, self.off, self.out)
         return self
 
+    def encode(self, out=True, precision="fp32"):
+        """The one-call encoder (abcs_encode): budget, sense and, with out,
+        the decoder's image."""
+        import paper_2001_09632_amd as g
+        g.encode(self.plan, self.px, self.k, self.off, self.stat, self.y, self.out if out else None,
+                 precision=precision)
+        return self
+
     def fetch(self):
         import torch
         torch.cuda.synchronize()

@@ -175,7 +175,8 @@ def test_runs_are_bitwise_repeatable():
 
 def test_batch_64x512_all_estimators_and_subrates():
     """The 64 x 512^2 batch with BBV and DD at C_R 0.1..0.5 in one plan, run
-    exactly as the benchmark launches it: every budget, statistic and offset
+    exactly as the benchmark launches it (abcs_encode: budget, then sensing
+    and the decoder in one pass): every budget, statistic and offset
     bit-exact; y and pixels compared in full on 8 images per combination."""
     seeds = list(range(1000, 1064))
     imgs = [synth.synth_image(s, 512, 512) for s in seeds]
@@ -186,7 +187,7 @@ def test_batch_64x512_all_estimators_and_subrates():
             for i in range(64):
                 entries.append(dict(d[i], block=16, subrate=cr, method=m))
                 cases.append((i, cr, orc.METHOD_NAMES[m]))
-    run = Run(px, entries).budget().sense().reconstruct().fetch()
+    run = Run(px, entries).encode().fetch()
     for j, (i, cr, m) in enumerate(cases):
         full = (i % 8 == 0)
         _check_image(run, j, imgs[i], 16, cr, m, check_y=full, check_px=full)
