@@ -152,6 +152,106 @@ def ida_workload():
     return imgs, crs, methods
 
 
+def judge_section(dev, plan, y, k, off, imgs, prm, capture=(1, 3, 5, 10, 20, 29)):
+    """The plain denoiser as judge of the learned one: pairs (v^t, sigma^t)
+    captured from the plain (BM3D) loop on the IDA batch (images never used
+    in training) at the iterations in `capture`, each denoised by the CNN
+    (with its fallback) and by BM3D; mean squared error against the clean
+    image, for the pairs whose sigma lies in the network's trained range and
+    for all pairs."""
+    import numpy as np
+    import torch
+    import paper_2001_09632_amd as g
+    n = plan.n
+    ws = torch.empty(g.ida_workspace_bytes(plan, "bm3d"), dtype=torch.uint8, device=dev)
+    wc = torch.empty(g.denoise_workspace_bytes(plan, "cnn"), dtype=torch.uint8, device=dev)
+    wb = torch.empty(g.denoise_workspace_bytes(plan, "bm3d"), dtype=torch.uint8, device=dev)
+    x = torch.zeros(plan.pixels, dtype=torch.float32, device=dev)
+    v = torch.empty_like(x)
+    oc, ob = torch.empty_like(x), torch.empty_like(x)
+    sig = torch.empty(n, dtype=torch.float32, device=dev)
+    lo, hi = float(prm[-2]), float(prm[-1])
+    mse_c, mse_b, inr = [], [], []
+    for t in range(max(capture) + 1):
+        g.ida_iterate(plan, y, k, off, x, t, t + 1, 2.0, "bm3d", sigma_trace=sig, v_last=v, workspace=ws)
+        if t not in capture:
+            continue
+        g.denoise(plan, v, sig, oc, "cnn", params=prm, workspace=wc)
+        g.denoise(plan, v, sig, ob, "bm3d", workspace=wb)
+        torch.cuda.synchronize()
+        hc, hb, hs = oc.cpu().numpy(), ob.cpu().numpy(), sig.cpu().numpy()
+        for i, im in enumerate(imgs):
+            d = plan.images[i]
+            ref = im.astype(np.float64).reshape(-1)
+            a = hc[d["out_offset"]:d["out_offset"] + im.size].astype(np.float64)
+            b = hb[d["out_offset"]:d["out_offset"] + im.size].astype(np.float64)
+            mse_c.append(float(np.mean((a - ref) ** 2)))
+            mse_b.append(float(np.mean((b - ref) ** 2)))
+            inr.append(lo <= float(hs[i]) <= hi)
+    mse_c, mse_b, inr = np.array(mse_c), np.array(mse_b), np.array(inr)
+    return {"pairs": int(mse_c.size), "iterations": list(capture), "trained_sigma_range": [lo, hi],
+            "in_range": {"pairs": int(inr.sum()), "cnn_mse": round(float(mse_c[inr].mean()), 3),
+                         "bm3d_mse": round(float(mse_b[inr].mean()), 3),
+                         "cnn_better_fraction": round(float(np.mean(mse_c[inr] < mse_b[inr])), 3)},
+            "all": {"cnn_mse": round(float(mse_c.mean()), 3), "bm3d_mse": round(float(mse_b.mean()), 3)}}
+
+
+def ida_oracle_sample(dev, imgs, prm, iters=5, size=64):
+    """Config 3 against the FP64 oracle on a bounded sample: the top-left
+    size x size crops of the IDA batch's first two images (DD at C_R 0.2,
+    BBV at 0.25), `iters` IDA iterations with BM3D and with the CNN on the GPU
+    and in the oracle (the oracle's CNN rounds weights and hidden activations
+    to bfloat16, as the network's arithmetic is defined, and falls back to
+    BM3D outside the trained sigma range); PSNR against the clean crop."""
+    import numpy as np
+    import torch
+    import paper_2001_09632_amd as g
+    from oracle import bm3d as obm3d, cnn as ocnn, ida as oida, metrics
+    from paper_2001_09632_amd.train import encode_batch
+    crops = [np.ascontiguousarray(im[:size, :size]) for im in imgs[:2]]
+    plan, y, k, off = encode_batch(dev, crops, [0.2, 0.25], ["dd", "bbv"])
+    pr = prm.cpu().numpy().astype(np.float64)
+    blob, lo, hi = pr[:-2], pr[-2], pr[-1]
+
+    def bf16(a):
+        u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+    layers = [(bf16(w), b) for w, b in ocnn.unpack(blob)]
+
+    def cnn_oracle(vv, sg):
+        if not (lo <= sg <= hi):
+            return obm3d.bm3d(vv, sg)
+        a = ocnn.network_input(vv[None], [sg])
+        for i, (w, b) in enumerate(layers):
+            a = ocnn.conv3x3(a, w, b)
+            if i < len(layers) - 1:
+                a = bf16(np.maximum(a, 0.0))
+        return vv - 255.0 * a[0, ..., 0]
+
+    yh, kh = y.cpu().numpy(), k.cpu().numpy()
+    out = {"sample": f"{len(crops)} crops of {size}x{size}, {iters} iterations, D_F = 2"}
+    for den, params, oden in (("bm3d", None, obm3d.bm3d), ("cnn", prm, cnn_oracle)):
+        ws = torch.empty(g.ida_workspace_bytes(plan, den), dtype=torch.uint8, device=dev)
+        x = torch.empty(plan.pixels, dtype=torch.float32, device=dev)
+        g.ida_refine(plan, y, k, off, x, iters, 2.0, den, params=params, workspace=ws)
+        torch.cuda.synchronize()
+        xh = x.cpu().numpy().astype(np.float64)
+        pg, po = [], []
+        for i, c in enumerate(crops):
+            d = plan.images[i]
+            nb = (size // 16) ** 2
+            yi = yh[d["meas_offset"]:d["meas_offset"] + d["n_meas"]].astype(np.float64)
+            xo, _ = oida.ida(yi, kh[d["block_offset"]:d["block_offset"] + nb], 16, size, size, iters, 2.0,
+                             denoiser=oden)
+            pg.append(metrics.psnr(xh[d["out_offset"]:d["out_offset"] + c.size].reshape(c.shape), c.astype(float)))
+            po.append(metrics.psnr(xo, c.astype(float)))
+        out[den] = {"psnr_gpu": round(float(np.mean(pg)), 4), "psnr_oracle": round(float(np.mean(po)), 4),
+                    "max_abs_dpsnr_db": round(float(np.max(np.abs(np.array(pg) - np.array(po)))), 4)}
+    return out
+
+
 def ida_section(dev, weights_path):
     """Plain IDA (BM3D, 30 iterations, D_F = 2) against learned IDA (CNN) on
     one mixed batch: images/s and PSNR/SSIM against the ground truth; the
@@ -224,6 +324,9 @@ def ida_section(dev, weights_path):
                       "psnr_by_iters": trail}
     rec["matched_psnr"] = matched
     rec["learned_over_plain_images_per_s"] = round(tp / tl, 2)
+
+    rec["judge"] = judge_section(dev, plan, y, k, off, imgs, prm)
+    rec["vs_oracle"] = ida_oracle_sample(dev, imgs, prm)
 
     # Roofline of the learned denoisers alone (one abcs_denoise call on the
     # batch, HIP events on the launch stream): algorithmic flops of the
@@ -459,10 +562,13 @@ def stream_section(dev, n_requests=1000, load=0.5):
     def run_batch(idx):
         return run_plan(make_plan(idx))
 
-    # Poisson arrivals at `load` of the saturated pixel rate
+    # Poisson arrivals at `load` of the saturated end-to-end pixel rate (the
+    # stream plans each batch when it forms, so planning is part of the
+    # service time)
     rng = np.random.default_rng(7)
     mean_px = total_px / n_requests
-    gaps = rng.exponential(mean_px / (load * sat_rate), size=n_requests)
+    e2e_rate = total_px / (sat_s + plan_total_s)
+    gaps = rng.exponential(mean_px / (load * e2e_rate), size=n_requests)
     arrive = np.cumsum(gaps)
     done = np.zeros(n_requests)
     nxt = 0
@@ -516,6 +622,35 @@ def bounds_section(dev, plan, px, k, out, images):
 
     res = {"encodings": plan.n, "pixels": plan.pixels}
     table = {"bbv": psnr(out)[0].tolist(), "dd": psnr(out)[1].tolist()}
+    # L-DCT-ZZ on the same images and subrates (the non-adaptive reference
+    # of Section VII-A), and the blocks each rule leaves with no coefficient
+    zz_plan = g.Plan([dict(e, method="zz") for e in entries()[:n_img * len(SUBRATES)]], features=())
+    kz = torch.empty(zz_plan.blocks, dtype=torch.int32, device=dev)
+    oz = torch.empty(zz_plan.blocks, dtype=torch.int64, device=dev)
+    sz = torch.empty(zz_plan.blocks, dtype=torch.int32, device=dev)
+    yz = torch.empty(zz_plan.meas, dtype=torch.float32, device=dev)
+    xz = torch.empty(zz_plan.pixels, dtype=torch.float32, device=dev)
+    g.encode(zz_plan, px, kz, oz, sz, yz, xz)
+    xz = xz.view(len(SUBRATES), n_img, H, W).clamp(0, 255)
+    table["zz"] = (10.0 * torch.log10(255.0 ** 2 / ((xz - ref[None]) ** 2).mean(dim=(2, 3)))).mean(dim=1).tolist()
+    nb = (H // B) * (W // B)
+    zero = (k.view(len(METHODS), len(SUBRATES), n_img, nb) == 0).sum(dim=3)       # per image
+    res["zero_budget_blocks_by_cr"] = {meth: {str(cr): int(zero[i, j].sum()) for j, cr in enumerate(SUBRATES)}
+                                       for i, meth in enumerate(METHODS)}
+    res["images_with_zero_budget_blocks_by_cr"] = {
+        meth: {str(cr): int((zero[i, j] > 0).sum()) for j, cr in enumerate(SUBRATES)} for i, meth in enumerate(METHODS)}
+    # the same PSNR table over the images where BBV leaves no block empty at
+    # any subrate (the saturated, perfectly flat areas of the other images
+    # carry no BBV weight, so those blocks get no coefficient at all)
+    clean_img = (zero[0].sum(dim=0) == 0)
+    x_ad = out.view(len(METHODS), len(SUBRATES), n_img, H, W)[:, :, clean_img].clamp(0, 255)
+    p_ad = (10.0 * torch.log10(255.0 ** 2 / ((x_ad - ref[clean_img][None, None]) ** 2).mean(dim=(3, 4)))).mean(dim=2)
+    p_zz = (10.0 * torch.log10(255.0 ** 2 / ((xz[:, clean_img] - ref[clean_img][None]) ** 2).mean(dim=(2, 3)))).mean(dim=1)
+    res["psnr_db_by_cr_without_zero_budget_images"] = {
+        "images": int(clean_img.sum()),
+        "bbv": {str(cr): round(v, 3) for cr, v in zip(SUBRATES, p_ad[0].tolist())},
+        "dd": {str(cr): round(v, 3) for cr, v in zip(SUBRATES, p_ad[1].tolist())},
+        "zz": {str(cr): round(v, 3) for cr, v in zip(SUBRATES, p_zz.tolist())}}
     for r in ("thi", "thb"):
         g.threshold(plan, px, m[r], dec, rule=r, workspace=ws)
         torch.cuda.synchronize()
@@ -699,6 +834,9 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a device-to-device copy of this many MiB (5 times) and exit; "
                          "its FETCH_SIZE / WRITE_SIZE readings calibrate the traffic counters")
+    ap.add_argument("--denoiser-probe", action="store_true",
+                    help="only run abcs_denoise with BM3D and with the CNN on the IDA batch's real-time decodings "
+                         "(sigma 25), 3 calls each, and exit: the workload of the denoisers' counter profiles")
     ap.add_argument("--bw-probe", type=float, default=0.0,
                     help="only time a device copy and a fill of this many MiB and print their HBM rates")
     args = ap.parse_args()
@@ -742,6 +880,27 @@ def main():
             ms = ev[0].elapsed_time(ev[1]) / 10
             out[name] = {"ms": round(ms, 4), "GB_per_s": round(moved / ms / 1e6, 1)}
         print(json.dumps(out))
+        return
+    if args.denoiser_probe:
+        from paper_2001_09632_amd.train import encode_batch, load_params
+        imgs, crs, methods = ida_workload()
+        dplan, dy, dk, doff = encode_batch(dev, imgs, crs, methods)
+        io = torch.empty(dplan.pixels, dtype=torch.float32, device=dev)
+        g.reconstruct(dplan, dy, dk, doff, io)
+        sig = torch.full((dplan.n,), 25.0, dtype=torch.float32, device=dev)
+        o = torch.empty_like(io)
+        prm = torch.from_numpy(load_params(args.cnn_weights)).to(dev)
+        rec = {}
+        for den, params in (("bm3d", None), ("cnn", prm)):
+            ws = torch.empty(g.denoise_workspace_bytes(dplan, den), dtype=torch.uint8, device=dev)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            for _ in range(3):
+                g.denoise(dplan, io, sig, o, den, params=params, workspace=ws)
+            ev[1].record()
+            torch.cuda.synchronize()
+            rec[den + "_ms_per_call"] = round(ev[0].elapsed_time(ev[1]) / 3, 3)
+        print(json.dumps({"denoiser_probe": rec, "pixels": dplan.pixels}))
         return
     log("generating images")
     images = make_images()
