@@ -6,7 +6,7 @@ Workload (one step): a batch of 64 synthetic 512x512 uint8 greyscale images
 AL-DCT-DD) at subrates 0.1, 0.2, 0.3, 0.4, 0.5 - 640 image encodings in one
 plan - run through phase-1 statistics + budget apportionment (abcs_budget)
 and phase-2 sensing with the masked inverse 2D-DCT decoder in one pass
-(abcs_sense_decode), float32: the two halves of abcs_encode.  Inputs are
+(abcs_sense_decode), float32: the two launches of abcs_encode.  Inputs are
 resident in HBM before timing starts.
 
 Prints one JSON line: Mpixel/s over the whole step, the roofline of the
@@ -117,6 +117,24 @@ TRAFFIC = {
         fetch_kib=98078.44, write_kib=655519.97,
         copy_fetch_kib=524301.26, copy_write_kib=1048576.0),
 }
+
+
+# Float32 arithmetic of one BM3D call on the IDA batch at sigma 25, counted
+# with rocprofv3 (SQ_INSTS_VALU_ADD/MUL/FMA/TRANS_F32, 64 lanes per wave
+# instruction, FMA = 2 flops; an upper bound, masked lanes count); keyed like
+# TRAFFIC by the sources that define the kernels.
+BM3D_FP32 = dict(sources=("csrc/bm3d_kernels.hpp", "build.py"),
+                 sha256="afad6da334fac26719b1e131d115e9efc9dab870fc8452e4747242a7fdc54161", flop_per_call=5.41e11)
+FP32_PEAK_TFLOPS = 157.3
+
+
+def counted_bm3d_flop():
+    import hashlib
+    h = hashlib.sha256()
+    for f in BM3D_FP32["sources"]:
+        with open(os.path.join(ROOT, "paper_2001_09632_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return BM3D_FP32["flop_per_call"] if h.hexdigest() == BM3D_FP32["sha256"] else None
 
 
 def measured_traffic(kind):
@@ -351,8 +369,16 @@ def ida_section(dev, weights_path):
         return {"ms_per_call": round(ms, 3), "bound": "mfma", "achieved": round(ach, 1), "peak": BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4), "algorithmic_flop": int(flop)}
 
+    bm3d_ms = denoise_ms("bm3d", None, reps=2)
+    bm3d_flop = counted_bm3d_flop()
     rec["denoiser_roofline"] = {"cnn": conv_roofline(denoise_ms("cnn", prm), 6),
-                                "bm3d_ms_per_call": round(denoise_ms("bm3d", None, reps=2), 3)}
+                                "bm3d_ms_per_call": round(bm3d_ms, 3),
+                                "bm3d": None if bm3d_flop is None else {
+                                    "ms_per_call": round(bm3d_ms, 3), "bound": "valu issue",
+                                    "counted_fp32_flop": bm3d_flop,
+                                    "achieved": round(bm3d_flop / (bm3d_ms * 1e-3) / 1e12, 1),
+                                    "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": round(bm3d_flop / (bm3d_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)}}
 
     # DnCNN-17 with batch normalisation (the paper's network, trained here by
     # the library's kernels): the same matched-PSNR rule.
@@ -914,9 +940,10 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
-        # abcs_encode's two halves, so that each launch can be timed:
-        # phase-1 statistics + apportionment, then sensing and the decoder in
-        # one pass over each tile
+        # abcs_encode's two launches, called as its two halves so that each
+        # can be timed: phase-1 statistics + apportionment (abcs_budget), then
+        # sensing and the decoder in one pass over each tile
+        # (abcs_sense_decode)
         if ev is not None:
             ev[0].record(stream)
         g.budget(plan, px, k, off, stat, stream)
@@ -958,8 +985,24 @@ def main():
                          basis="(1 + 4 y/pixel + 4 + 12/B^2) bytes per pixel over ms_per_step")
     per_kernel_ms = dict(budget=round(ms_budget, 4), sense_decode=round(ms_sd, 4))
 
-    # The same step as three calls (budget, sense, reconstruct: the decoder
-    # reads y back), for comparison.
+    # The same step in one launch (abcs_encode with a workspace: statistics,
+    # apportionment, sensing and decoding in k_encode_fused, after a fill of
+    # its synchronisation words), for comparison; same bits.
+    y1, out1 = y.clone(), out.clone()
+    ws_enc = torch.empty(max(1, g.encode_workspace_bytes(plan)), dtype=torch.uint8, device=dev)
+    assert g.encode_workspace_bytes(plan) > 0, "the step's plan should be eligible for the one-launch encoder"
+    e1 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for rep in range(2):
+        e1[0].record(stream)
+        for _ in range(10):
+            g.encode(plan, px, k, off, stat, y, out, stream, workspace=ws_enc)
+        e1[1].record(stream)
+        torch.cuda.synchronize()
+    per_kernel_ms["encode_one_launch"] = round(e1[0].elapsed_time(e1[1]) / 10, 4)
+    assert torch.equal(y, y1) and torch.equal(out, out1), "the one-launch encoder differs from the two launches"
+    assert int(ws_enc[4:8].view(torch.int32).item()) == 0, "the one-launch encoder's wait gave up"
+
+    # and as three calls (budget, sense, reconstruct: the decoder reads y back)
     y32, out32 = y.clone(), out.clone()
     e3 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     for rep in range(2):
@@ -1049,7 +1092,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "64 synthetic 512x512 uint8 images, B=16, AL-DCT-BBV and AL-DCT-DD at C_R "
                                "0.1/0.2/0.3/0.4/0.5 (640 encodings per step): budget + sense + masked inverse DCT "
-                               "(abcs_budget, then abcs_sense_decode: 2 launches)",
+                               "(abcs_budget, then abcs_sense_decode: the 2 launches of abcs_encode)",
                    "images": len(SEEDS), "height": H, "width": W, "block": B, "encodings_per_step": plan.n,
                    "pixels_per_step": pixels_per_step},
         "per_kernel_ms": per_kernel_ms,

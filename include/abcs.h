@@ -210,14 +210,30 @@ int abcs_reconstruct(const abcs_plan* plan, const float* d_y, const int32_t* d_k
  * image alongside: abcs_budget (phase-1 statistics, apportionment, offsets),
  * then abcs_sense, then, when d_out is not NULL, the image abcs_reconstruct
  * would decode from the same y (an encoder's local decoder, as in the
- * real-time system of Fig 1).  For float32 16 x 16 images sensing and
- * decoding are one pass over each tile: the decoder takes the coefficients
- * from the forward transform instead of reading y back, with the same
- * arithmetic as abcs_reconstruct, so d_out equals abcs_reconstruct's output
- * bit for bit.  Arguments and errors as the three calls; d_out nullable,
- * float[pixels], 16-byte aligned. */
+ * real-time system of Fig 1).  The decoder takes the coefficients from the
+ * forward transform instead of reading y back, with the same arithmetic as
+ * abcs_reconstruct, so d_out equals abcs_reconstruct's output bit for bit.
+ * When every image of the plan is a 16 x 16 DCT image of at most 1024
+ * blocks, precision is float32, d_out is not NULL and d_ws holds
+ * abcs_encode_workspace_bytes(plan) bytes (0 for other plans; its contents on
+ * entry do not matter), everything runs in one launch (after a fill of the
+ * workspace): statistics, each image's apportionment as soon as its
+ * statistics are complete, then sensing and decoding of its tiles, one work
+ * item per workgroup in one ticket order that always makes progress (word 1
+ * of the workspace is set if a tile ever gave up waiting for its budgets; it
+ * never should).  Otherwise (d_ws NULL included) the budget runs as its own
+ * launches and sensing with decoding as one more, and d_ws is not used.
+ * Both give the same bits.  The one launch is the slower of the two on a
+ * batch that fills the chip (0.44 ms against 0.29 ms for 640 encodings of
+ * 512 x 512): each image's statistics must be published across the chip's
+ * XCDs, whose L2 caches are not coherent, and the fences that do this write
+ * back or invalidate a whole L2; between two launches this happens once. */
+ * Arguments and errors as the three calls; d_out nullable, float[pixels],
+ * 16-byte aligned; d_ws nullable, 4-byte aligned. */
+size_t abcs_encode_workspace_bytes(const abcs_plan* plan);
 int abcs_encode(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, int32_t* d_k,
-                int64_t* d_offsets, int32_t* d_stat, float* d_y, float* d_out, int precision, void* stream);
+                int64_t* d_offsets, int32_t* d_stat, float* d_y, float* d_out, int precision, void* d_ws,
+                size_t ws_bytes, void* stream);
 /* The second half of abcs_encode on its own (budgets already in d_k and
  * d_offsets): abcs_sense and the decoder's image in d_out (not NULL). */
 int abcs_sense_decode(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, const int32_t* d_k,

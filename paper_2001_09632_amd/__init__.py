@@ -6,7 +6,7 @@ tensors to raw pointers and the current HIP stream; every step of the method
 runs in the gfx950 kernels of libabcs.so.  There is no CPU fallback: calls
 raise if the library is missing.
 """
-from .api import (ZZ, BBV, DD, Plan, AbcsError, budget, sense, reconstruct, encode, sense_decode,  # noqa: F401
+from .api import (ZZ, BBV, DD, Plan, AbcsError, budget, sense, reconstruct, encode, sense_decode, encode_workspace_bytes,  # noqa: F401
                   dct_basis, METHODS, ida_refine, ida_iterate, ida_workspace_bytes, DENOISERS,
                   denoise, denoise_workspace_bytes, cnn_param_count, cnn_train_step,
                   cnn_train_workspace_bytes, IdaGraph, PRECISIONS,

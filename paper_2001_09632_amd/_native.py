@@ -17,7 +17,7 @@ EXPORTS = [
     "abcs_threshold_workspace_bytes", "abcs_threshold", "abcs_budget_correlation",
     "abcs_bbv_samples", "ida_refine_bbv",
     "abcs_dncnn_param_count", "abcs_dncnn_running_count", "abcs_dncnn_train_workspace_bytes",
-    "abcs_dncnn_train_step", "abcs_workspace_part", "abcs_encode", "abcs_sense_decode",
+    "abcs_dncnn_train_step", "abcs_workspace_part", "abcs_encode", "abcs_sense_decode", "abcs_encode_workspace_bytes",
     "ida_noalloc_scratch_bytes", "ida_refine_noalloc",
 ]
 
@@ -67,7 +67,9 @@ def lib():
     L.abcs_budget.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.abcs_sense.argtypes = [vp, vp, i64, vp, vp, vp, i32, vp]
     L.abcs_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, vp]
-    L.abcs_encode.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, i32, vp]
+    L.abcs_encode.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, i32, vp, sz, vp]
+    L.abcs_encode_workspace_bytes.argtypes = [vp]
+    L.abcs_encode_workspace_bytes.restype = sz
     L.abcs_sense_decode.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, vp]
     L.abcs_dct_basis.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
     L.abcs_last_error.restype = ctypes.c_char_p
@@ -114,7 +116,8 @@ def lib():
                         "amp_workspace_bytes", "abcs_threshold_workspace_bytes",
                         "abcs_dncnn_param_count", "abcs_dncnn_running_count", "abcs_dncnn_train_workspace_bytes",
                         "abcs_denoise_workspace_bytes", "abcs_cnn_param_count",
-                        "abcs_cnn_train_workspace_bytes", "ida_noalloc_scratch_bytes"):
+                        "abcs_cnn_train_workspace_bytes", "ida_noalloc_scratch_bytes",
+                        "abcs_encode_workspace_bytes"):
             f.restype = ctypes.c_int
     _lib = L
     return L

@@ -116,11 +116,19 @@ IDENTITY, BM3D, CNN, DNCNN = 0, 1, 2, 3
 DENOISERS = {"identity": IDENTITY, "bm3d": BM3D, "cnn": CNN, "dncnn": DNCNN}
 
 
-def encode(plan, px, k, offsets, stat, y, out=None, stream=None, precision="fp32"):
+def encode_workspace_bytes(plan):
+    return int(lib().abcs_encode_workspace_bytes(plan.handle))
+
+
+def encode(plan, px, k, offsets, stat, y, out=None, stream=None, precision="fp32", workspace=None):
     """abcs_encode: budget + sense (+ the decoder's image into out, float32
-    [pixels], when given) in one call."""
+    [pixels], when given) in one call; with a workspace of
+    encode_workspace_bytes(plan) bytes an eligible plan runs in one
+    launch."""
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     check(lib().abcs_encode(plan.handle, _ptr(px), px.numel() * px.element_size(), _ptr(k), _ptr(offsets),
-                            _ptr(stat), _ptr(y), _ptr(out), _prec(precision), _stream(stream)))
+                            _ptr(stat), _ptr(y), _ptr(out), _prec(precision), _ptr(workspace), ws_bytes,
+                            _stream(stream)))
 
 
 def sense_decode(plan, px, k, offsets, y, out, stream=None, precision="fp32"):

@@ -126,13 +126,20 @@ __device__ __forceinline__ void dd_flush(const uint16_t* list, int n, const uint
   wave_lds_sync();
 }
 
+// LDS of the DD statistics of one workgroup (four waves).
+struct DDStatsLds {
+  PxStage stage[kWavesPerGroup];
+  uint16_t ulist[kWavesPerGroup][kDDListCap];
+  int32_t ucount[kWavesPerGroup][kTileBlocks];
+};
+
 template <int XF>
 __device__ __forceinline__ void dd_stats_group(const ImgDev* __restrict__ imgs, const Tile* __restrict__ tiles,
                                                int ntiles, const uint8_t* __restrict__ px,
-                                               int32_t* __restrict__ stat, int group) {
-  __shared__ PxStage stage[kWavesPerGroup];
-  __shared__ uint16_t ulist[kWavesPerGroup][kDDListCap];
-  __shared__ int32_t ucount[kWavesPerGroup][kTileBlocks];
+                                               int32_t* __restrict__ stat, int group, DDStatsLds& sl) {
+  PxStage* stage = sl.stage;
+  uint16_t (*ulist)[kDDListCap] = sl.ulist;
+  int32_t (*ucount)[kTileBlocks] = sl.ucount;
   const double* Dd = Basis16<XF>::Dd();
   const int wave = group * kWavesPerGroup + wave_in_group();
   if (wave >= ntiles) return;
@@ -210,10 +217,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_phase1_stats(const ImgDev* __
                                                                int g_bbv, const Tile* __restrict__ tiles_dd,
                                                                int nt_dd, const uint8_t* __restrict__ px,
                                                                int32_t* __restrict__ stat) {
+  __shared__ DDStatsLds sl;
   if ((int)blockIdx.x < g_bbv)
     bbv_stats_thread(imgs, tiles_bbv, nt_bbv, px, stat, blockIdx.x * kGroupThreads + threadIdx.x);
   else
-    dd_stats_group<kXfDCT>(imgs, tiles_dd, nt_dd, px, stat, blockIdx.x - g_bbv);
+    dd_stats_group<kXfDCT>(imgs, tiles_dd, nt_dd, px, stat, blockIdx.x - g_bbv, sl);
 }
 
 // DD statistics of 16x16 Walsh-Hadamard tiles (one wavefront per tile).
@@ -221,7 +229,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_dd_stats16_wht(const ImgDev* 
                                                                  const Tile* __restrict__ tiles, int ntiles,
                                                                  const uint8_t* __restrict__ px,
                                                                  int32_t* __restrict__ stat) {
-  dd_stats_group<kXfWHT>(imgs, tiles, ntiles, px, stat, blockIdx.x);
+  __shared__ DDStatsLds sl;
+  dd_stats_group<kXfWHT>(imgs, tiles, ntiles, px, stat, blockIdx.x, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -620,16 +629,21 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
 // LDS only, and global memory is read once and written once.  For images of
 // at most kThreads * kPer blocks; the steps and their results are those of
 // k_apportion.
+template <int kThreads>
+struct ApportionLds {
+  int64_t sh64[kThreads / 64];
+  int32_t hist[256];
+  int64_t sel_sh[2];
+};
+
 template <int kThreads, int kPer>
-__global__ __launch_bounds__(kThreads) void k_apportion_reg(const ImgDev* __restrict__ imgs,
-                                                            int32_t* __restrict__ stat_all,
-                                                            int32_t* __restrict__ k_all,
-                                                            int64_t* __restrict__ off_all) {
+__device__ __forceinline__ void apportion_image_reg(const ImgDev& im, int32_t* __restrict__ stat_all,
+                                                    int32_t* __restrict__ k_all, int64_t* __restrict__ off_all,
+                                                    ApportionLds<kThreads>& al) {
   constexpr int kWaves = kThreads / 64;
-  __shared__ int64_t sh64[kWaves];
-  __shared__ int32_t hist[256];
-  __shared__ int64_t sel_sh[2];
-  const ImgDev im = imgs[blockIdx.x];
+  int64_t* sh64 = al.sh64;
+  int32_t* hist = al.hist;
+  int64_t* sel_sh = al.sel_sh;
   const int nB = im.nB;
   int32_t* wg = stat_all + im.blk_off;
   int32_t* kg = k_all + im.blk_off;
@@ -763,6 +777,15 @@ __global__ __launch_bounds__(kThreads) void k_apportion_reg(const ImgDev* __rest
       og[i0 + j] = base;
       base += kv[j];
     }
+}
+
+template <int kThreads, int kPer>
+__global__ __launch_bounds__(kThreads) void k_apportion_reg(const ImgDev* __restrict__ imgs,
+                                                            int32_t* __restrict__ stat_all,
+                                                            int32_t* __restrict__ k_all,
+                                                            int64_t* __restrict__ off_all) {
+  __shared__ ApportionLds<kThreads> al;
+  apportion_image_reg<kThreads, kPer>(imgs[blockIdx.x], stat_all, k_all, off_all, al);
 }
 
 }  // namespace abcs

@@ -203,20 +203,22 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
 // forward products of the next pair of blocks are issued before the current
 // pair's stores and inverse, so that the matrix cores have work while the
 // wave waits on LDS and memory.
-template <int XF = kXfDCT>
-__global__ __launch_bounds__(kGroupThreads) void k_encode16(const ImgDev* __restrict__ imgs,
-                                                           const Tile* __restrict__ tiles, int ntiles,
-                                                           const uint8_t* __restrict__ px,
-                                                           const int32_t* __restrict__ k_all,
-                                                           const int64_t* __restrict__ off_all,
-                                                           float* __restrict__ y, float* __restrict__ out) {
+// LDS of one workgroup of k_encode16: per wave two coefficient buffers and the
+// tile's pixels.
+struct EncodeLds {
+  WaveLds coef[kWavesPerGroup][2];
+  PxStage stage[kWavesPerGroup];
+};
+
+// One wave's tile (see k_encode16).
+template <int XF>
+__device__ __forceinline__ void encode16_tile(const ImgDev& im, const Tile& tl, const uint8_t* __restrict__ px,
+                                              const int32_t* __restrict__ k_all,
+                                              const int64_t* __restrict__ off_all, float* __restrict__ y,
+                                              float* __restrict__ out, EncodeLds& el) {
   typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
-  __shared__ WaveLds lds[kWavesPerGroup][2];
-  __shared__ PxStage stage[kWavesPerGroup];
-  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
-  if (wave >= ntiles) return;
-  const Tile tl = tiles[wave];
-  const ImgDev im = imgs[tl.img];
+  WaveLds (*lds)[2] = el.coef;
+  PxStage* stage = el.stage;
   Lane16 L;
   lane16_init<XF>(L);
   Lane16T T;
@@ -299,6 +301,20 @@ __global__ __launch_bounds__(kGroupThreads) void k_encode16(const ImgDev* __rest
     C[0] = Cn[0];
     C[1] = Cn[1];
   }
+}
+
+template <int XF = kXfDCT>
+__global__ __launch_bounds__(kGroupThreads) void k_encode16(const ImgDev* __restrict__ imgs,
+                                                           const Tile* __restrict__ tiles, int ntiles,
+                                                           const uint8_t* __restrict__ px,
+                                                           const int32_t* __restrict__ k_all,
+                                                           const int64_t* __restrict__ off_all,
+                                                           float* __restrict__ y, float* __restrict__ out) {
+  __shared__ EncodeLds el;
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= ntiles) return;
+  const Tile tl = tiles[wave];
+  encode16_tile<XF>(imgs[tl.img], tl, px, k_all, off_all, y, out, el);
 }
 
 }  // namespace abcs

@@ -105,3 +105,59 @@ def test_plan_without_optional_tables():
     with pytest.raises(g.AbcsError, match="ABCS_PLAN_BOUNDS"):
         g.threshold(run.plan, run.px, m, rule="thi", workspace=tws)
     torch.cuda.synchronize()
+
+
+def _fused_entries():
+    """A plan the one-launch encoder takes: 16 x 16 DCT images of at most 1024
+    blocks, every rule (ZZ, BBV with and without samples, DD), ragged sizes,
+    images of one block row and of a single block."""
+    sizes = [(512, 512), (64, 48), (170, 181), (16, 16), (96, 500), (250, 130), (48, 272)]
+    imgs = [synth.synth_image(5200 + i, h, w) for i, (h, w) in enumerate(sizes)]
+    px, d = pack_images(imgs, pitch_pad=12)
+    ent = []
+    for i in range(len(imgs)):
+        for m, cr in (("dd", 0.1), ("bbv", 0.3), ("zz", 0.2), ("bbv", 0.05), ("dd", 0.5), ("bbv", 0.5)):
+            ent.append(dict(d[i], block=16, subrate=cr, method=m))
+    return px, ent
+
+
+def test_one_launch_encoder_equals_separate_calls():
+    import torch
+    import paper_2001_09632_amd as g
+    px, ent = _fused_entries()
+    a = Run(px, ent).budget().sense().reconstruct().fetch()
+    b = Run(px, ent)
+    nbytes = g.encode_workspace_bytes(b.plan)
+    assert nbytes > 0
+    ws = torch.full((nbytes,), 0x55, dtype=torch.uint8, device=b.px.device)   # contents do not matter
+    for rep in range(3):                       # the workspace is reused as is
+        b.out.fill_(float("nan"))
+        g.encode(b.plan, b.px, b.k, b.off, b.stat, b.y, b.out, workspace=ws)
+        b.fetch()
+        _same(a, b)
+        assert int(ws[4:8].view(torch.int32).item()) == 0   # no tile gave up waiting
+
+
+def test_one_launch_encoder_on_the_benchmark_batch():
+    """The 640-encoding batch (64 x 512^2, BBV and DD at five subrates):
+    the one-launch encoder against the separate calls, bit for bit."""
+    import torch
+    import paper_2001_09632_amd as g
+    imgs = [synth.synth_image(s, 512, 512) for s in range(1000, 1064)]
+    px, d = pack_images(imgs)
+    ent = [dict(d[i], block=16, subrate=cr, method=m) for m in ("bbv", "dd") for cr in (0.1, 0.2, 0.3, 0.4, 0.5)
+           for i in range(64)]
+    a = Run(px, ent).budget().sense().reconstruct().fetch()
+    b = Run(px, ent)
+    ws = torch.empty(g.encode_workspace_bytes(b.plan), dtype=torch.uint8, device=b.px.device)
+    g.encode(b.plan, b.px, b.k, b.off, b.stat, b.y, b.out, workspace=ws)
+    _same(a, b.fetch())
+
+
+def test_encoder_workspace_only_for_eligible_plans():
+    import paper_2001_09632_amd as g
+    px, ent = _entries()                      # B = 8 and 32 and Walsh images: not eligible
+    run = Run(px, ent)
+    assert g.encode_workspace_bytes(run.plan) == 0
+    big = g.Plan([dict(height=1024, width=1024, block=16, subrate=0.2, method="dd", pixel_offset=0)], features=())
+    assert g.encode_workspace_bytes(big) == 0  # 4096 blocks: beyond the one-launch apportionment
