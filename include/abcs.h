@@ -86,9 +86,10 @@ typedef enum abcs_transform {
   ABCS_WHT = 1
 } abcs_transform;
 
-/* Arithmetic of the B = 16 DCT transforms in abcs_sense and
- * abcs_reconstruct (B = 8 and 32, and B = 16 Walsh-Hadamard images, always
- * use the float32 matrix cores).  The 16-bit modes run on the matrix cores with float32 sums; the
+/* Arithmetic of the DCT transforms (B = 8, 16 and 32) in abcs_sense,
+ * abcs_reconstruct, abcs_sense_decode and abcs_encode (Walsh-Hadamard images
+ * always use the float32 matrix cores: their forward transform is exact
+ * there).  The 16-bit modes run on the matrix cores with float32 sums; the
  * "x3" modes split each operand that is not exact in 16 bits into a high and a
  * low part and keep every product but low x low (about float32 accuracy); the
  * single-pass modes round the operands once.  Budgets (abcs_budget) never
@@ -227,7 +228,7 @@ int abcs_reconstruct(const abcs_plan* plan, const float* d_y, const int32_t* d_k
  * batch that fills the chip (0.44 ms against 0.29 ms for 640 encodings of
  * 512 x 512): each image's statistics must be published across the chip's
  * XCDs, whose L2 caches are not coherent, and the fences that do this write
- * back or invalidate a whole L2; between two launches this happens once. */
+ * back or invalidate a whole L2; between two launches this happens once.
  * Arguments and errors as the three calls; d_out nullable, float[pixels],
  * 16-byte aligned; d_ws nullable, 4-byte aligned. */
 size_t abcs_encode_workspace_bytes(const abcs_plan* plan);

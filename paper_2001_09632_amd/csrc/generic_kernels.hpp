@@ -386,6 +386,113 @@ __device__ __forceinline__ void idct32_inv(const float e[2][2][4], const Lane32&
     }
 }
 
+// The 16-bit modes of the B = 32 products (see the precision modes of the
+// 16x16 transforms): one v_mfma_f32_16x16x{16bf16_1k,16f16} takes the four K
+// slots 4g .. 4g+3 that four float32 products take, so a lane's operands of a
+// 16x16 tile product pack into one 16-bit 4-vector.  The split modes keep hi
+// x hi, hi x lo and lo x hi of every stage; pixels are exact in 16 bits.
+template <int P>
+struct Lane32P {
+  u16x4 r_hi[2][2], r_lo[2][2], t_hi[2][2], t_lo[2][2];  // dR and dT, split
+};
+
+template <int P>
+__device__ __forceinline__ void lane32p_init(Lane32P<P>& H, const Lane32& L) {
+  constexpr bool BF = Prec16<P>::kBF;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      split16<BF>(L.dR[a][b], H.r_hi[a][b], H.r_lo[a][b]);
+      split16<BF>(L.dT[a][b], H.t_hi[a][b], H.t_lo[a][b]);
+    }
+}
+
+// dct32_fwd in precision P (same layouts)
+template <int P>
+__device__ __forceinline__ void dct32_fwd_p(const float x[2][2][4], const Lane32P<P>& H, f32x4 C[2][2]) {
+  constexpr bool BF = Prec16<P>::kBF, SP = Prec16<P>::kSplit;
+  u16x4 xs[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) xs[i][k][c] = to16<BF>(x[i][k][c]);
+  u16x4 th[2][2], tl[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      f32x4 t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        t = mfma16<BF>(xs[i][k], H.r_hi[j][k], t);  // T = X D^T
+        if (SP) t = mfma16<BF>(xs[i][k], H.r_lo[j][k], t);
+      }
+      const float tv[4] = {t[0], t[1], t[2], t[3]};
+      split16<BF>(tv, th[i][j], tl[i][j]);
+    }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      f32x4 o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        o = mfma16<BF>(H.r_hi[i][k], th[k][j], o);  // C = D T
+        if (SP) {
+          o = mfma16<BF>(H.r_hi[i][k], tl[k][j], o);
+          o = mfma16<BF>(H.r_lo[i][k], th[k][j], o);
+        }
+      }
+      C[i][j] = o;
+    }
+}
+
+// idct32_inv in precision P (same layouts)
+template <int P>
+__device__ __forceinline__ void idct32_inv_p(const float e[2][2][4], const Lane32P<P>& H, f32x4 X[2][2]) {
+  constexpr bool BF = Prec16<P>::kBF, SP = Prec16<P>::kSplit;
+  u16x4 eh[2][2], el[2][2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) split16<BF>(e[k][i], eh[k][i], el[k][i]);
+  u16x4 qh[2][2], ql[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      f32x4 q = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        q = mfma16<BF>(eh[k][i], H.t_hi[k][j], q);  // Q = C^T D
+        if (SP) {
+          q = mfma16<BF>(el[k][i], H.t_hi[k][j], q);
+          q = mfma16<BF>(eh[k][i], H.t_lo[k][j], q);
+        }
+      }
+      const float qv[4] = {q[0], q[1], q[2], q[3]};
+      split16<BF>(qv, qh[i][j], ql[i][j]);
+    }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      f32x4 o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        o = mfma16<BF>(H.t_hi[k][i], qh[k][j], o);  // X^T = D^T Q
+        if (SP) {
+          o = mfma16<BF>(H.t_hi[k][i], ql[k][j], o);
+          o = mfma16<BF>(H.t_lo[k][i], qh[k][j], o);
+        }
+      }
+      X[i][j] = o;
+    }
+}
+
 struct WaveLds32 {
   float c[1024];
 };
@@ -393,7 +500,7 @@ struct WaveLds32 {
 // y[off_i + z] = C_i[zigzag[z]] for z < k_i (B = 32): the block's
 // coefficients go to LDS at their zigzag rank, then leave in unit-stride
 // stores of k_i values.
-template <int XF>
+template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restrict__ imgs,
                                                           const Tile* __restrict__ tiles, int ntiles,
                                                           const uint8_t* __restrict__ px,
@@ -407,6 +514,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restr
   const ImgDev im = imgs[tl.img];
   Lane32 L;
   lane32_init<XF>(L);
+  Lane32P<P> H;
+  if constexpr (P != kPrecFP32) lane32p_init<P>(H, L);
   const int lane = threadIdx.x & 63;
   int zr[2][2][4];  // zigzag rank of coefficient (16i + 4g + r, 16j + n)
 #pragma unroll
@@ -434,7 +543,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restr
         for (int c = 0; c < 4; ++c) x[i][k][c] = (float)((w >> (8 * c)) & 0xffu);
       }
     f32x4 C[2][2];
-    dct32_fwd(x, L, C);
+    if constexpr (P == kPrecFP32)
+      dct32_fwd(x, L, C);
+    else
+      dct32_fwd_p<P>(x, H, C);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -456,7 +568,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restr
 // out = D^T C D per block (B = 32), C zero beyond the block's k_i zigzag
 // entries: the block's coefficients are staged in LDS in zigzag order (zero
 // past k_i) and gathered in the inverse's operand layout.
-template <int XF>
+template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* __restrict__ imgs,
                                                                 const Tile* __restrict__ tiles, int ntiles,
                                                                 const float* __restrict__ y,
@@ -471,6 +583,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* _
   const ImgDev im = imgs[tl.img];
   Lane32 L;
   lane32_init<XF>(L);
+  Lane32P<P> H;
+  if constexpr (P != kPrecFP32) lane32p_init<P>(H, L);
   const int lane = threadIdx.x & 63;
   int zr[2][2][4];  // zigzag rank of coefficient (16k + 4g + c, 16i + n)
 #pragma unroll
@@ -505,7 +619,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* _
         for (int c = 0; c < 4; ++c) e[k][i][c] = buf[zr[k][i][c]];
     wave_lds_sync();
     f32x4 X[2][2];
-    idct32_inv(e, L, X);
+    if constexpr (P == kPrecFP32)
+      idct32_inv(e, L, X);
+    else
+      idct32_inv_p<P>(e, H, X);
     // X[i][j][r] = pixel (16j + n, 16i + 4g + r)
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -551,7 +668,7 @@ struct WaveLds8 {
   float c[4][64];
 };
 
-template <int XF>
+template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_sense8(const ImgDev* __restrict__ imgs,
                                                          const Tile* __restrict__ tiles, int ntiles,
                                                          const uint8_t* __restrict__ px,
@@ -565,6 +682,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense8(const ImgDev* __restri
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane8x4_init<XF>(L);
+  Lane16P<P> H;  // the block-diagonal basis split for the 16-bit modes
+  if constexpr (P != kPrecFP32) lane16p_init<P>(H, L);
   const int lane = threadIdx.x & 63;
   // operand side: block quadrant and pixel row / column of this lane
   const int xq = 2 * (L.n >> 3) + (L.g >> 1), xrow = L.n & 7, xcol = 4 * (L.g & 1);
@@ -587,7 +706,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense8(const ImgDev* __restri
     float a[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) a[c] = (float)((w >> (8 * c)) & 0xffu);
-    const f32x4 C = dct16_fwd(a, L);
+    f32x4 C;
+    if constexpr (P == kPrecFP32)
+      C = dct16_fwd(a, L);
+    else
+      C = dct16_fwd_p<P>(a, H);
 #pragma unroll
     for (int r = 0; r < 4; ++r) buf.c[oq][zr[r]] = C[r];
     wave_lds_sync();
@@ -605,7 +728,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense8(const ImgDev* __restri
   }
 }
 
-template <int XF>
+template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_reconstruct8(const ImgDev* __restrict__ imgs,
                                                                const Tile* __restrict__ tiles, int ntiles,
                                                                const float* __restrict__ y,
@@ -620,6 +743,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct8(const ImgDev* __
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane8x4_init<XF>(L);
+  Lane16P<P> H;  // the block-diagonal basis split for the 16-bit modes
+  if constexpr (P != kPrecFP32) lane16p_init<P>(H, L);
   const int lane = threadIdx.x & 63;
   const int xq = 2 * (L.n >> 3) + (L.g >> 1), xrow = L.n & 7, xcol = 4 * (L.g & 1);
   const int oq = 2 * (L.g >> 1) + (L.n >> 3);
@@ -647,7 +772,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct8(const ImgDev* __
 #pragma unroll
     for (int c = 0; c < 4; ++c) e[c] = buf.c[oq][zr[c]];
     wave_lds_sync();
-    const f32x4 X = idct16_inv(e, L);
+    f32x4 X;
+    if constexpr (P == kPrecFP32)
+      X = idct16_inv(e, L);
+    else
+      X = idct16_inv_p<P>(e, H);
     const int bx = b0 + xq;
     const uint32_t off = bx < tl.count ? 4u * (uint32_t)(xrow * im.Wc + 8 * bx + xcol) : 0xffffffffu;
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X), rout, off, 0, kStoreNT);
