@@ -111,11 +111,11 @@ def precision_errors(plan, out_host, sample, images):
 # after any change the figure is null until the counters are taken again.
 COPY_KIB = 1048576.0
 TRAFFIC = {
-    "reconstruct": dict(
+    "sense_decode": dict(
         sources=("csrc/common.hpp", "csrc/transform16.hpp", "csrc/sense_kernels.hpp", "build.py"),
-        sha256="09a4468b9463b3d0014580f20071dd38097e85d3d6f70f786737b8be6cf37784",
-        fetch_kib=98078.44, write_kib=655519.97,
-        copy_fetch_kib=524301.26, copy_write_kib=1048576.0),
+        sha256="e4e3b4f8c856df083b4362b811fe0d93d072a27197fb440021112d39b6dd4d0c",
+        fetch_kib=59281.19, write_kib=840652.0,
+        copy_fetch_kib=524301.24, copy_write_kib=1048576.0),
 }
 
 
@@ -454,7 +454,7 @@ def ida_section(dev, weights_path):
 
 
 STREAM_SIZES = [(256, 256), (512, 512), (768, 1024), (2048, 2048)]   # (H, W); 1024x768 read as W x H
-STREAM_BUDGET_BYTES = 1 << 30   # device bytes of y + decoded images admitted per batch
+STREAM_BUDGET_BYTES = 1 << 30   # device bytes of y, decoded images and per-block arrays admitted per batch
 
 
 def single_image_section(dev, reps=200):
@@ -505,6 +505,52 @@ def stream_requests(n, seed=5):
             for _ in range(n)]
 
 
+def stream_precision_errors(dev, reqs, pool, offs, px, entry, n_sample=24):
+    """Every precision mode on a sample of the stream's requests (the first
+    n_sample of size at most 1024x768: all three block sizes, rules and a
+    spread of C_R) in one plan: largest |pixel - oracle pixel| and mean /
+    largest |dPSNR| (clean image as reference), the oracle decoding its own
+    float64 measurements with the same budgets (the GPU's budgets equal the
+    oracle's, checked here too)."""
+    import numpy as np
+    import torch
+    import paper_2001_09632_amd as g
+    from oracle import abcs as orc
+    from oracle import metrics
+    idx = [i for i, r in enumerate(reqs) if STREAM_SIZES[r["size"]][0] * STREAM_SIZES[r["size"]][1] <= 1024 * 768]
+    idx = idx[:n_sample]
+    plan = g.Plan([entry(reqs[i]) for i in idx], features=())
+    k = torch.empty(plan.blocks, dtype=torch.int32, device=dev)
+    off = torch.empty(plan.blocks, dtype=torch.int64, device=dev)
+    st = torch.empty(plan.blocks, dtype=torch.int32, device=dev)
+    y = torch.empty(plan.meas, dtype=torch.float32, device=dev)
+    out = torch.empty(plan.pixels, dtype=torch.float32, device=dev)
+    g.budget(plan, px, k, off, st)
+    kh = k.cpu().numpy()
+    refs = []
+    for j, i in enumerate(idx):
+        r, d = reqs[i], plan.images[j]
+        img = pool[r["size"]]
+        kk, _ = orc.budget(img, r["block"], r["subrate"], orc.METHOD_NAMES[r["method"]])
+        assert np.array_equal(kh[d["block_offset"]:d["block_offset"] + kk.size], kk), "budget differs from the oracle"
+        h, w = img.shape
+        refs.append((orc.reconstruct(orc.sense(img, r["block"], kk), r["block"], kk, h, w), d))
+    res = {"sample": f"{len(idx)} requests (B 8/16/32, ZZ/BBV/DD, sizes up to 1024x768)"}
+    for mode in g.PRECISIONS:
+        g.sense_decode(plan, px, k, off, y, out, precision=mode)
+        oh = out.cpu().numpy()
+        mx, dp = 0.0, []
+        for (ref, d), i in zip(refs, idx):
+            hc, wc = d["cropped_height"], d["cropped_width"]
+            got = oh[d["out_offset"]:d["out_offset"] + hc * wc].reshape(hc, wc).astype(np.float64)
+            clean = pool[reqs[i]["size"]][:hc, :wc].astype(np.float64)
+            mx = max(mx, float(np.max(np.abs(got - ref))))
+            dp.append(abs(metrics.psnr(got, clean) - metrics.psnr(ref, clean)))
+        res[mode] = {"max_abs_dpx_vs_oracle": round(mx, 6), "mean_abs_dpsnr_db": round(float(np.mean(dp)), 6),
+                     "max_abs_dpsnr_db": round(float(np.max(dp)), 6)}
+    return res
+
+
 def stream_section(dev, n_requests=1000, load=0.5):
     """The mixed request stream: every request is encoded (budget + sense) and
     decoded (masked inverse DCT) on the GPU with abcs_encode.  Requests are
@@ -532,22 +578,13 @@ def stream_section(dev, n_requests=1000, load=0.5):
         return dict(height=h, width=w, row_pitch=w, block=r["block"], subrate=r["subrate"], method=r["method"],
                     pixel_offset=offs[r["size"]])
 
-    def cost(r):
-        h, w = STREAM_SIZES[r["size"]]
-        return 4 * h * w + 4 * int(r["subrate"] * h * w) + 64
+    # admission control: requests join the open batch in arrival order while
+    # the batch's outputs (y, decoded images, per-block arrays) fit the budget
+    admission = g.Admission(STREAM_BUDGET_BYTES)
 
     def batches(order):
-        out, cur, used = [], [], 0
-        for i in order:
-            c = cost(reqs[i])
-            if cur and used + c > STREAM_BUDGET_BYTES:
-                out.append(cur)
-                cur, used = [], 0
-            cur.append(i)
-            used += c
-        if cur:
-            out.append(cur)
-        return out
+        order = list(order)
+        return [[order[j] for j in b] for b in admission.batches([entry(reqs[i]) for i in order])]
 
     max_blocks = max(sum((STREAM_SIZES[reqs[i]["size"]][0] // reqs[i]["block"]) *
                          (STREAM_SIZES[reqs[i]["size"]][1] // reqs[i]["block"]) for i in b)
@@ -605,16 +642,19 @@ def stream_section(dev, n_requests=1000, load=0.5):
             time.sleep(arrive[nxt] - now)
             now = time.perf_counter() - t0
         ready = [i for i in range(nxt, n_requests) if arrive[i] <= now]
-        batch = batches(ready)[0]
+        batch = [ready[j] for j in admission.first_batch([entry(reqs[i]) for i in ready])]
         run_batch(batch)
         done[batch] = time.perf_counter() - t0
         nxt = batch[-1] + 1
     span = done.max()
     lat = (done - arrive) * 1e3
+    prec = stream_precision_errors(dev, reqs, pool, offs, px, entry)
     n_sat = len(batches(range(n_requests)))
     stream_plans = plan_s[n_sat:]
     return {"workload": f"{n_requests} requests: 256x256 / 512x512 / 1024x768 / 2048x2048 uniform, B 8/16/32, "
-                        "C_R ~ U(0.05,0.5), ZZ/BBV/DD; abcs_encode (budget+sense+inverse DCT), plan per batch",
+                        "C_R ~ U(0.05,0.5), ZZ/BBV/DD; abcs_encode (budget+sense+inverse DCT), plan per batch, "
+                        "batches formed by the library's Admission (outputs within the budget, arrival order), "
+                        "launch splits from the tuned table",
             "pixels": int(total_px), "batch_budget_bytes": STREAM_BUDGET_BYTES,
             "saturated": {"mpixel_per_s": round(sat_rate / 1e6, 1), "seconds": round(sat_s, 4),
                           "batches": n_sat, "plan_seconds": round(plan_total_s, 4),
@@ -622,7 +662,8 @@ def stream_section(dev, n_requests=1000, load=0.5):
             "stream": {"offered_load": load, "mpixel_per_s": round(total_px / span / 1e6, 1),
                        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                                       "p99": round(float(np.percentile(lat, 99)), 3)},
-                       "plan_ms_mean": round(1e3 * float(np.mean(stream_plans)), 3) if stream_plans else None}}
+                       "plan_ms_mean": round(1e3 * float(np.mean(stream_plans)), 3) if stream_plans else None},
+            "precision_vs_oracle": prec}
 
 
 def bounds_section(dev, plan, px, k, out, images):
@@ -928,6 +969,15 @@ def main():
             rec[den + "_ms_per_call"] = round(ev[0].elapsed_time(ev[1]) / 3, 3)
         print(json.dumps({"denoiser_probe": rec, "pixels": dplan.pixels}))
         return
+    # launch splits of the sensing and decoding kernels: the stored table of
+    # this build, or a tuning run now (about a minute) when there is none
+    from paper_2001_09632_amd import tune
+    t_tune = time.perf_counter()
+    table, tune_source = tune.ensure(log=log)
+    launch_tuning = {"source": tune_source, "build_id": table["build_id"],
+                     "seconds": round(time.perf_counter() - t_tune, 2), "size_classes": table["size_classes"],
+                     "splits": tune.splits_summary(table)}
+
     log("generating images")
     images = make_images()
     px = torch.from_numpy(images.reshape(-1)).to(dev)
@@ -1096,6 +1146,7 @@ def main():
                    "images": len(SEEDS), "height": H, "width": W, "block": B, "encodings_per_step": plan.n,
                    "pixels_per_step": pixels_per_step},
         "per_kernel_ms": per_kernel_ms,
+        "launch_tuning": launch_tuning,
         "precision_modes": prec,
         "single_image": single,
         "roofline": roofline,

@@ -168,6 +168,12 @@ void abcs_plan_destroy(abcs_plan* plan);
  * buffer).  Any pointer may be NULL. */
 int abcs_plan_totals(const abcs_plan* plan, int64_t* h_blocks, int64_t* h_meas,
                      int64_t* h_pixels);
+/* The totals one descriptor would add to a plan (blocks, coefficients in y,
+ * decoded pixels), with the same validation and errors as abcs_plan_create
+ * and nothing else: host only, no device, no allocation.  For admission
+ * control: a request's device bytes follow from these before any plan is
+ * made. */
+int abcs_image_totals(const abcs_image* h_img, int64_t* h_blocks, int64_t* h_meas, int64_t* h_pixels);
 /* Copy descriptor i, with its layout fields filled, into *h_out. */
 int abcs_plan_image(const abcs_plan* plan, int i, abcs_image* h_out);
 
@@ -239,6 +245,46 @@ int abcs_encode(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, in
  * d_offsets): abcs_sense and the decoder's image in d_out (not NULL). */
 int abcs_sense_decode(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, const int32_t* d_k,
                       const int64_t* d_offsets, float* d_y, float* d_out, int precision, void* stream);
+
+/* Launch tuning (not part of the method: how its sensing and decoding
+ * kernels are spread over the chip).  Those kernels give each tile (up to 16
+ * horizontally adjacent blocks of one image) to one wavefront; a split s in
+ * {0, 1, 2} gives it to 2^s wavefronts of 16 / 2^s blocks each, which fills
+ * the chip's 1024 SIMDs better when a batch has few tiles and costs a little
+ * per-wave set-up on large ones.  Results never depend on the split.  The
+ * library keeps one split per (block size, transform, precision, size class),
+ * the size class of a launch being that of its tile count: 0 below 256
+ * tiles, 1 below 2048, 2 below 16384, 3 above (Walsh-Hadamard launches are
+ * float32 and use the ABCS_FP32 entry).  All splits are 0 until a table is
+ * set; the table is global to the process and read by every launch of
+ * abcs_sense, abcs_reconstruct, abcs_sense_decode and abcs_encode. */
+typedef struct abcs_launch_entry {
+  int32_t block;       /* 8, 16 or 32 */
+  int32_t transform;   /* abcs_transform */
+  int32_t precision;   /* abcs_precision */
+  int32_t size_class;  /* 0 .. 3 */
+  int32_t split;       /* 0 .. 2 */
+} abcs_launch_entry;
+/* Replace the table: every split not named in entries[0..n) becomes 0 (n = 0
+ * resets).  EINVAL on an entry out of range (the table is then unchanged). */
+int abcs_set_launch_table(const abcs_launch_entry* entries, int n);
+/* The split in force for a launch kind (>= 0), or EINVAL. */
+int abcs_launch_split(int block, int transform, int precision, int size_class);
+/* Size class of the plan's tiles of one kind, -1 if the plan has none, or
+ * EINVAL. */
+int abcs_plan_size_class(const abcs_plan* plan, int block, int transform);
+/* The tuner's measurement: abcs_sense_decode on the plan (arguments as
+ * there; budgets already in d_k and d_offsets) with every launch forced to
+ * split s, for s = 0, 1, 2: one warm-up call, then reps timed calls between
+ * two events on `stream`; h_ms[s] receives the mean milliseconds per call.
+ * Waits for the device; no other call may use the library while it runs
+ * (the forced split is process-wide). */
+int abcs_time_splits(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, const int32_t* d_k,
+                     const int64_t* d_offsets, float* d_y, float* d_out, int precision, int reps, float* h_ms,
+                     void* stream);
+/* Identity of this build: a hash of the library's sources and compiler
+ * flags, under which tuning results are stored. */
+const char* abcs_build_id(void);
 
 /* IDA post-processing (Section VI; eqs 13, 15, 25, 28; Fig 6).
  * Starting from x^0 = 0 and z^{-1} = 0, iteration t = 0 .. iters-1 computes

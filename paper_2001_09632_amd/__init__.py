@@ -14,4 +14,6 @@ from .api import (ZZ, BBV, DD, Plan, AbcsError, budget, sense, reconstruct, enco
                   threshold_workspace_bytes, budget_correlation, RULES, TRANSFORMS,
                   bbv_samples, ida_refine_bbv, dncnn_param_count, dncnn_running_count,
                   dncnn_train_workspace_bytes, dncnn_train_step, workspace_part,
-                  ida_refine_noalloc, ida_noalloc_scratch_bytes, denoiser_params)
+                  ida_refine_noalloc, ida_noalloc_scratch_bytes, denoiser_params,
+                  set_launch_table, launch_split, plan_size_class, time_splits, build_id, image_totals)
+from .admission import Admission  # noqa: F401

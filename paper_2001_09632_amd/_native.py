@@ -19,7 +19,13 @@ EXPORTS = [
     "abcs_dncnn_param_count", "abcs_dncnn_running_count", "abcs_dncnn_train_workspace_bytes",
     "abcs_dncnn_train_step", "abcs_workspace_part", "abcs_encode", "abcs_sense_decode", "abcs_encode_workspace_bytes",
     "ida_noalloc_scratch_bytes", "ida_refine_noalloc",
+    "abcs_image_totals", "abcs_set_launch_table", "abcs_launch_split", "abcs_plan_size_class", "abcs_time_splits", "abcs_build_id",
 ]
+
+
+class LaunchEntry(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("transform", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("size_class", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 class AbcsError(RuntimeError):
@@ -64,6 +70,7 @@ def lib():
     L.abcs_plan_destroy.restype = None
     L.abcs_plan_totals.argtypes = [vp, P64, P64, P64]
     L.abcs_plan_image.argtypes = [vp, i32, ctypes.POINTER(ImageDesc)]
+    L.abcs_image_totals.argtypes = [ctypes.POINTER(ImageDesc), P64, P64, P64]
     L.abcs_budget.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.abcs_sense.argtypes = [vp, vp, i64, vp, vp, vp, i32, vp]
     L.abcs_reconstruct.argtypes = [vp, vp, vp, vp, vp, i32, vp]
@@ -108,6 +115,11 @@ def lib():
     L.ida_noalloc_scratch_bytes.restype = sz
     L.ida_refine_noalloc.argtypes = [vp, vp, vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp]
     L.abcs_workspace_part.argtypes = [vp, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.abcs_set_launch_table.argtypes = [ctypes.POINTER(LaunchEntry), i32]
+    L.abcs_launch_split.argtypes = [i32, i32, i32, i32]
+    L.abcs_plan_size_class.argtypes = [vp, i32, i32]
+    L.abcs_time_splits.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, i32, ctypes.POINTER(ctypes.c_float), vp]
+    L.abcs_build_id.argtypes = []
     L.ida_graph_destroy.argtypes = [vp]
     L.ida_graph_destroy.restype = None
     for name in EXPORTS:
@@ -117,8 +129,9 @@ def lib():
                         "abcs_dncnn_param_count", "abcs_dncnn_running_count", "abcs_dncnn_train_workspace_bytes",
                         "abcs_denoise_workspace_bytes", "abcs_cnn_param_count",
                         "abcs_cnn_train_workspace_bytes", "ida_noalloc_scratch_bytes",
-                        "abcs_encode_workspace_bytes"):
+                        "abcs_encode_workspace_bytes", "abcs_build_id"):
             f.restype = ctypes.c_int
+    L.abcs_build_id.restype = ctypes.c_char_p
     _lib = L
     return L
 

@@ -21,6 +21,35 @@ def _stream(stream):
 TRANSFORMS = {"dct": 0, "wht": 1}
 
 
+def _fill_desc(out, d, offset=0):
+    """Fill an ImageDesc from a dict (see Plan); returns the next packed
+    pixel offset."""
+    m = d["method"]
+    m = METHODS[m] if isinstance(m, str) else int(m)
+    pitch = int(d.get("row_pitch", (int(d["width"]) + 3) // 4 * 4))
+    po = d.get("pixel_offset")
+    if po is None:
+        po = offset
+        offset += pitch * int(d["height"])
+        offset = (offset + 3) // 4 * 4
+    out.height, out.width, out.row_pitch = int(d["height"]), int(d["width"]), pitch
+    out.block, out.subrate, out.method = int(d["block"]), float(d["subrate"]), m
+    xf = d.get("transform", "dct")
+    out.transform = TRANSFORMS[xf] if isinstance(xf, str) else int(xf)
+    out.pixel_offset = int(po)
+    return offset
+
+
+def image_totals(d):
+    """abcs_image_totals: (blocks, coefficients, decoded pixels) one
+    descriptor dict (as for Plan) adds to a plan; host only."""
+    desc = ImageDesc()
+    _fill_desc(desc, d)
+    b, m, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(lib().abcs_image_totals(ctypes.byref(desc), ctypes.byref(b), ctypes.byref(m), ctypes.byref(p)))
+    return b.value, m.value, p.value
+
+
 class Plan:
     """A validated batch of images (abcs_plan_create).
 
@@ -40,19 +69,7 @@ class Plan:
         arr = (ImageDesc * max(1, len(imgs)))()
         offset = 0
         for i, d in enumerate(imgs):
-            m = d["method"]
-            m = METHODS[m] if isinstance(m, str) else int(m)
-            pitch = int(d.get("row_pitch", (int(d["width"]) + 3) // 4 * 4))
-            po = d.get("pixel_offset")
-            if po is None:
-                po = offset
-                offset += pitch * int(d["height"])
-                offset = (offset + 3) // 4 * 4
-            arr[i].height, arr[i].width, arr[i].row_pitch = int(d["height"]), int(d["width"]), pitch
-            arr[i].block, arr[i].subrate, arr[i].method = int(d["block"]), float(d["subrate"]), m
-            xf = d.get("transform", "dct")
-            arr[i].transform = TRANSFORMS[xf] if isinstance(xf, str) else int(xf)
-            arr[i].pixel_offset = int(po)
+            offset = _fill_desc(arr[i], d, offset)
         self._h = ctypes.c_void_p()
         flags = 0
         for f in features:
@@ -353,3 +370,48 @@ def dct_basis(block):
     buf = (ctypes.c_double * (block * block))()
     check(lib().abcs_dct_basis(int(block), buf))
     return [[buf[u * block + j] for j in range(block)] for u in range(block)]
+
+
+def set_launch_table(entries):
+    """abcs_set_launch_table: entries of dicts with block, transform ('dct' /
+    'wht' or 0 / 1), precision (PRECISIONS name or value), size_class,
+    split; every split not named becomes 0 (an empty list resets)."""
+    from ._native import LaunchEntry
+    arr = (LaunchEntry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        tr = e.get("transform", "dct")
+        arr[i] = LaunchEntry(int(e["block"]), TRANSFORMS[tr] if isinstance(tr, str) else int(tr),
+                             _prec(e["precision"]), int(e["size_class"]), int(e["split"]))
+    check(lib().abcs_set_launch_table(arr, len(entries)))
+
+
+def launch_split(block, transform, precision, size_class):
+    """abcs_launch_split: the split in force for a launch kind."""
+    r = lib().abcs_launch_split(int(block), TRANSFORMS[transform] if isinstance(transform, str) else int(transform),
+                                _prec(precision), int(size_class))
+    if r < 0:
+        check(r)
+    return r
+
+
+def plan_size_class(plan, block, transform="dct"):
+    """abcs_plan_size_class: size class of the plan's tiles of one kind, or
+    -1 when the plan has none."""
+    r = lib().abcs_plan_size_class(plan.handle, int(block),
+                                   TRANSFORMS[transform] if isinstance(transform, str) else int(transform))
+    if r < -1:
+        check(r)
+    return r
+
+
+def time_splits(plan, px, k, offsets, y, out, precision="fp32", reps=10, stream=None):
+    """abcs_time_splits: mean ms per abcs_sense_decode call at splits 0, 1, 2."""
+    ms = (ctypes.c_float * 3)()
+    check(lib().abcs_time_splits(plan.handle, _ptr(px), px.numel() * px.element_size(), _ptr(k), _ptr(offsets),
+                                 _ptr(y), _ptr(out), _prec(precision), int(reps), ms, _stream(stream)))
+    return [float(v) for v in ms]
+
+
+def build_id():
+    """abcs_build_id: hash of the library's sources and compiler flags."""
+    return lib().abcs_build_id().decode()

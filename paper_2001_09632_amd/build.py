@@ -22,10 +22,23 @@ def sources():
         os.path.join(os.path.dirname(PKG), "include", "abcs.h")]
 
 
+def build_id():
+    """SHA-256 (first 16 hex digits) of the sources and the compiler flags:
+    the library reports it (abcs_build_id), and launch-tuning results are
+    kept under it."""
+    import hashlib
+    h = hashlib.sha256(" ".join(FLAGS).encode())
+    for f in sources():
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose=False):
     """Compile libabcs.so; raises CalledProcessError on failure."""
     inc = os.path.join(os.path.dirname(PKG), "include")
-    cmd = [HIPCC] + FLAGS + ["-I", inc, "-o", LIB + ".tmp", os.path.join(CSRC, "libabcs.hip")]
+    cmd = [HIPCC] + FLAGS + ["-I", inc, f'-DABCS_BUILD_ID="{build_id()}"', "-o", LIB + ".tmp",
+                             os.path.join(CSRC, "libabcs.hip")]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)

@@ -52,6 +52,24 @@ struct Tile {
   int64_t out_base;// float offset of the first block's top-left decoded pixel
 };
 
+// Launch split: a launch of the sensing and decoding kernels may give each
+// tile to 2^split wavefronts (split 0 .. 2), wave w taking run w % 2^split,
+// of kTileBlocks >> split blocks, of tile w >> split.  The run is a tile of
+// its own (count 0 when it starts past the tile's end), so the kernels treat
+// it as any other tile.  B is the block size (pixels per block column).
+constexpr int kMaxSplit = 2;
+__device__ __forceinline__ Tile split_tile(const Tile* tiles, int w, int split, int B) {
+  Tile t = tiles[w >> split];
+  const int per = kTileBlocks >> split;
+  const int b0 = (w & ((1 << split) - 1)) * per;
+  const int c = t.count - b0;
+  t.first += b0;
+  t.count = c < 0 ? 0 : (c < per ? c : per);
+  t.px_base += (int64_t)b0 * B;
+  t.out_base += (int64_t)b0 * B;
+  return t;
+}
+
 // Index of the calling wavefront inside its workgroup, as a scalar (the
 // compiler cannot prove threadIdx.x >> 6 uniform on its own, and everything
 // derived from it would otherwise live in vector registers).

@@ -502,15 +502,16 @@ struct WaveLds32 {
 // stores of k_i values.
 template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restrict__ imgs,
-                                                          const Tile* __restrict__ tiles, int ntiles,
+                                                          const Tile* __restrict__ tiles, int ntiles, int split,
                                                           const uint8_t* __restrict__ px,
                                                           const int32_t* __restrict__ k_all,
                                                           const int64_t* __restrict__ off_all,
                                                           float* __restrict__ y) {
   __shared__ WaveLds32 lds[kWavesPerGroup];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
-  if (wave >= ntiles) return;
-  const Tile tl = tiles[wave];
+  if (wave >= (ntiles << split)) return;
+  const Tile tl = split_tile(tiles, wave, split, 32);
+  if (tl.count == 0) return;
   const ImgDev im = imgs[tl.img];
   Lane32 L;
   lane32_init<XF>(L);
@@ -570,7 +571,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restr
 // past k_i) and gathered in the inverse's operand layout.
 template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* __restrict__ imgs,
-                                                                const Tile* __restrict__ tiles, int ntiles,
+                                                                const Tile* __restrict__ tiles, int ntiles, int split,
                                                                 const float* __restrict__ y,
                                                                 const int32_t* __restrict__ k_all,
                                                                 const int64_t* __restrict__ off_all,
@@ -578,8 +579,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* _
   typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
   __shared__ WaveLds32 lds[kWavesPerGroup];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
-  if (wave >= ntiles) return;
-  const Tile tl = tiles[wave];
+  if (wave >= (ntiles << split)) return;
+  const Tile tl = split_tile(tiles, wave, split, 32);
+  if (tl.count == 0) return;
   const ImgDev im = imgs[tl.img];
   Lane32 L;
   lane32_init<XF>(L);
@@ -670,15 +672,16 @@ struct WaveLds8 {
 
 template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_sense8(const ImgDev* __restrict__ imgs,
-                                                         const Tile* __restrict__ tiles, int ntiles,
+                                                         const Tile* __restrict__ tiles, int ntiles, int split,
                                                          const uint8_t* __restrict__ px,
                                                          const int32_t* __restrict__ k_all,
                                                          const int64_t* __restrict__ off_all,
                                                          float* __restrict__ y) {
   __shared__ WaveLds8 lds[kWavesPerGroup];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
-  if (wave >= ntiles) return;
-  const Tile tl = tiles[wave];
+  if (wave >= (ntiles << split)) return;
+  const Tile tl = split_tile(tiles, wave, split, 8);
+  if (tl.count == 0) return;
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane8x4_init<XF>(L);
@@ -730,7 +733,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense8(const ImgDev* __restri
 
 template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_reconstruct8(const ImgDev* __restrict__ imgs,
-                                                               const Tile* __restrict__ tiles, int ntiles,
+                                                               const Tile* __restrict__ tiles, int ntiles, int split,
                                                                const float* __restrict__ y,
                                                                const int32_t* __restrict__ k_all,
                                                                const int64_t* __restrict__ off_all,
@@ -738,8 +741,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct8(const ImgDev* __
   typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
   __shared__ WaveLds8 lds[kWavesPerGroup];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
-  if (wave >= ntiles) return;
-  const Tile tl = tiles[wave];
+  if (wave >= (ntiles << split)) return;
+  const Tile tl = split_tile(tiles, wave, split, 8);
+  if (tl.count == 0) return;
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane8x4_init<XF>(L);

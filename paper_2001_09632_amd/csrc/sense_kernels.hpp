@@ -30,7 +30,7 @@ struct WaveLds {
 // work on.
 template <int P, int XF = kXfDCT>
 __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restrict__ imgs,
-                                                          const Tile* __restrict__ tiles, int ntiles,
+                                                          const Tile* __restrict__ tiles, int ntiles, int split,
                                                           const uint8_t* __restrict__ px,
                                                           const int32_t* __restrict__ k_all,
                                                           const int64_t* __restrict__ off_all,
@@ -38,8 +38,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
   __shared__ WaveLds lds[kWavesPerGroup][2];
   __shared__ PxStage stage[kWavesPerGroup];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
-  if (wave >= ntiles) return;
-  const Tile tl = tiles[wave];
+  if (wave >= (ntiles << split)) return;
+  const Tile tl = split_tile(tiles, wave, split, 16);
+  if (tl.count == 0) return;
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane16_init<XF>(L);
@@ -109,7 +110,7 @@ constexpr int kStoreNT = 2;
 
 template <int P, int XF = kXfDCT>
 __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* __restrict__ imgs,
-                                                                const Tile* __restrict__ tiles, int ntiles,
+                                                                const Tile* __restrict__ tiles, int ntiles, int split,
                                                                 const float* __restrict__ y,
                                                                 const int32_t* __restrict__ k_all,
                                                                 const int64_t* __restrict__ off_all,
@@ -117,8 +118,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
   typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
   __shared__ WaveLds lds[kWavesPerGroup][2];
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
-  if (wave >= ntiles) return;
-  const Tile tl = tiles[wave];
+  if (wave >= (ntiles << split)) return;
+  const Tile tl = split_tile(tiles, wave, split, 16);
+  if (tl.count == 0) return;
   const ImgDev im = imgs[tl.img];
   Lane16 L;
   lane16_init<XF>(L);
@@ -305,15 +307,16 @@ __device__ __forceinline__ void encode16_tile(const ImgDev& im, const Tile& tl, 
 
 template <int XF = kXfDCT>
 __global__ __launch_bounds__(kGroupThreads) void k_encode16(const ImgDev* __restrict__ imgs,
-                                                           const Tile* __restrict__ tiles, int ntiles,
+                                                           const Tile* __restrict__ tiles, int ntiles, int split,
                                                            const uint8_t* __restrict__ px,
                                                            const int32_t* __restrict__ k_all,
                                                            const int64_t* __restrict__ off_all,
                                                            float* __restrict__ y, float* __restrict__ out) {
   __shared__ EncodeLds el;
   const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
-  if (wave >= ntiles) return;
-  const Tile tl = tiles[wave];
+  if (wave >= (ntiles << split)) return;
+  const Tile tl = split_tile(tiles, wave, split, 16);
+  if (tl.count == 0) return;
   encode16_tile<XF>(imgs[tl.img], tl, px, k_all, off_all, y, out, el);
 }
 
