@@ -175,7 +175,7 @@ def judge_section(dev, plan, y, k, off, imgs, prm, capture=(1, 3, 5, 10, 20, 29)
     captured from the plain (BM3D) loop on the IDA batch (images never used
     in training) at the iterations in `capture`, each denoised by the CNN
     (with its fallback) and by BM3D; mean squared error against the clean
-    image, for the pairs whose sigma lies in the network's trained range and
+    image, for the pairs whose sigma lies in the network's accepted range and
     for all pairs."""
     import numpy as np
     import torch
@@ -207,7 +207,8 @@ def judge_section(dev, plan, y, k, off, imgs, prm, capture=(1, 3, 5, 10, 20, 29)
             mse_b.append(float(np.mean((b - ref) ** 2)))
             inr.append(lo <= float(hs[i]) <= hi)
     mse_c, mse_b, inr = np.array(mse_c), np.array(mse_b), np.array(inr)
-    return {"pairs": int(mse_c.size), "iterations": list(capture), "trained_sigma_range": [lo, hi],
+    return {"pairs": int(mse_c.size), "iterations": list(capture),
+            "accepted_sigma_range": [lo, hi if np.isfinite(hi) else "inf"],
             "in_range": {"pairs": int(inr.sum()), "cnn_mse": round(float(mse_c[inr].mean()), 3),
                          "bm3d_mse": round(float(mse_b[inr].mean()), 3),
                          "cnn_better_fraction": round(float(np.mean(mse_c[inr] < mse_b[inr])), 3)},

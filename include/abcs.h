@@ -68,12 +68,12 @@ typedef enum abcs_denoiser {
   ABCS_DENOISE_BM3D = 1,     /* plain BM3D (Dabov et al., ref [22])          */
   ABCS_DENOISE_CNN = 2,      /* learned 8-layer 3x3 CNN; parameters: the
                                 weight blob (abcs_cnn_param_count floats)
-                                followed by the trained noise range [lo, hi]
-                                (2 floats)                                  */
+                                followed by the accepted noise range
+                                [lo, hi] (2 floats, hi may be +inf)         */
   ABCS_DENOISE_DNCNN = 3     /* DnCNN-17 with batch normalisation (Section
                                 VI-4); parameters: the blob, the running
                                 statistics (abcs_dncnn_*_count), then the
-                                trained noise range [lo, hi]                */
+                                accepted noise range [lo, hi]               */
 } abcs_denoiser;
 
 /* Sensing transform of an image (Section IV): the 2-D DCT-II, or the 2-D
@@ -413,8 +413,10 @@ void ida_graph_destroy(abcs_ida_graph* graph);
  * search, groups of at most 16 / 32 (thresholds 2500 / 400 on ||P-Q||^2/64),
  * 8x8 DCT + Haar 3D transform, hard threshold 2.7 sigma, Wiener second stage,
  * Kaiser (beta 2) aggregation; results are bit-identical from run to run.
- * The learned denoisers (parameters in d_params: the weights, then the noise
- * range [lo, hi] the network was trained on) fall back to BM3D for every
+ * The learned denoisers (parameters in d_params: the weights, then the range
+ * [lo, hi] of sigma whose network input the training covered: the sigma
+ * channel is min(sigma, 255) / 255, so a network trained on noise up to 255
+ * or more accepts every larger sigma, hi = +inf) fall back to BM3D for every
  * image whose sigma lies outside [lo, hi] (NaN included) or whose network
  * output holds a non-finite value; the decision is taken on the device, and
  * BM3D's kernels skip the other images.  A NaN sigma gives a NaN image.
@@ -500,7 +502,7 @@ int abcs_budget_correlation(const abcs_plan* plan, const int32_t* d_m, const int
  * statistics hold per middle layer mean [64] then variance [64]
  * (abcs_dncnn_running_count floats).  As a denoiser (ABCS_DENOISE_DNCNN) the
  * parameter pointer addresses the blob immediately followed by the running
- * statistics and the trained noise range [lo, hi]; normalisation is folded
+ * statistics and the accepted noise range [lo, hi]; normalisation is folded
  * into the convolutions (inference). */
 size_t abcs_dncnn_param_count(void);
 size_t abcs_dncnn_running_count(void);

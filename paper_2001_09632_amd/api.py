@@ -280,8 +280,8 @@ def denoise(plan, x_in, sigma, x_out, denoiser="bm3d", params=None, workspace=No
 def denoiser_params(weights, sigma_range):
     """Parameter block of a learned denoiser as abcs_denoise / ida_refine take
     it: the network's float32 weights (for DnCNN followed by its running
-    statistics), then the noise range [lo, hi] the network was trained on
-    (images whose sigma lies outside it are denoised by BM3D)."""
+    statistics), then the range [lo, hi] of sigma the network accepts (hi
+    may be inf; images whose sigma lies outside it are denoised by BM3D)."""
     import numpy as np
     lo, hi = sigma_range
     return np.concatenate([np.asarray(weights, dtype=np.float32).reshape(-1),

@@ -276,7 +276,7 @@ def test_cnn_falls_back_to_bm3d_on_non_finite_output():
 
 
 def test_cnn_falls_back_to_bm3d_outside_its_sigma_range():
-    """Per image: sigma inside the trained range -> the network's output;
+    """Per image: sigma inside the accepted range -> the network's output;
     outside it -> BM3D's; a NaN sigma (no estimate) -> NaN, from either
     denoiser, never a stale buffer."""
     import torch

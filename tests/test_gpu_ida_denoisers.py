@@ -77,7 +77,7 @@ def _gpu_ida(run, iters, denoiser, params=None):
 def cnn_bf16_denoiser(params):
     """The learned denoiser as its arithmetic is defined: weights and hidden
     activations rounded to bfloat16, sums in float64; an image whose sigma
-    lies outside the trained range (the last two parameters) goes to BM3D."""
+    lies outside the accepted range (the last two parameters) goes to BM3D."""
     blob, (lo, hi) = params[:-2], params[-2:]
     layers = [(bf16_round(w), b) for w, b in ocnn.unpack(blob)]
 

@@ -30,7 +30,7 @@ def test_graph_replays_match_eager(denoiser, iters):
     plan = run.plan
     params = None
     if denoiser == "cnn":
-        # a narrow trained range, so that the BM3D fallback runs inside the
+        # a narrow accepted range, so that the BM3D fallback runs inside the
         # graph for the images whose sigma leaves it
         params = torch.from_numpy(g.denoiser_params(ocnn.init_params(5), (1.0, 150.0))).to(dev)
     nbytes = g.ida_workspace_bytes(plan, denoiser)
