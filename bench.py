@@ -107,12 +107,12 @@ def precision_errors(plan, out_host, sample, images):
 # WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads for
 # a plain device copy of 1 GiB (`bench.py --copy-probe 1024`).  A reading holds
 # only for the kernel it was taken on, so it is keyed by the SHA-256 of the
-# files that define the kernel and of the build script (its compiler flags);
-# after any change the figure is null until the counters are taken again.
+# files that define the kernel and of the compiler flags (source_key); after
+# any change the figure is null until the counters are taken again.
 COPY_KIB = 1048576.0
 TRAFFIC = {
     "sense_decode": dict(
-        sources=("csrc/common.hpp", "csrc/transform16.hpp", "csrc/sense_kernels.hpp", "build.py"),
+        sources=("csrc/common.hpp", "csrc/transform16.hpp", "csrc/sense_kernels.hpp"),
         sha256="e4e3b4f8c856df083b4362b811fe0d93d072a27197fb440021112d39b6dd4d0c",
         fetch_kib=59281.19, write_kib=840652.0,
         copy_fetch_kib=524301.24, copy_write_kib=1048576.0),
@@ -123,31 +123,30 @@ TRAFFIC = {
 # with rocprofv3 (SQ_INSTS_VALU_ADD/MUL/FMA/TRANS_F32, 64 lanes per wave
 # instruction, FMA = 2 flops; an upper bound, masked lanes count); keyed like
 # TRAFFIC by the sources that define the kernels.
-BM3D_FP32 = dict(sources=("csrc/bm3d_kernels.hpp", "build.py"),
-                 sha256="afad6da334fac26719b1e131d115e9efc9dab870fc8452e4747242a7fdc54161", flop_per_call=5.41e11)
+BM3D_FP32 = dict(sources=("csrc/bm3d_kernels.hpp",),
+                 sha256="c80b853ef68f0b13700bfe76ba2726cd8650924277379dbcea376c0f3bca4f93", flop_per_call=5.41e11)
 FP32_PEAK_TFLOPS = 157.3
 
 
-def counted_bm3d_flop():
+def source_key(sources):
+    """SHA-256 of the files that define a kernel and of the compiler flags."""
     import hashlib
-    h = hashlib.sha256()
-    for f in BM3D_FP32["sources"]:
+    from paper_2001_09632_amd import build
+    h = hashlib.sha256(" ".join(build.FLAGS).encode())
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2001_09632_amd", f), "rb") as fh:
             h.update(fh.read())
-    return BM3D_FP32["flop_per_call"] if h.hexdigest() == BM3D_FP32["sha256"] else None
+    return h.hexdigest()
+
+
+def counted_bm3d_flop():
+    return BM3D_FP32["flop_per_call"] if source_key(BM3D_FP32["sources"]) == BM3D_FP32["sha256"] else None
 
 
 def measured_traffic(kind):
     """HBM bytes per launch from the counter readings above, or None."""
-    import hashlib
     t = TRAFFIC.get(kind)
-    if t is None:
-        return None
-    h = hashlib.sha256()
-    for f in t["sources"]:
-        with open(os.path.join(ROOT, "paper_2001_09632_amd", f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != t["sha256"]:
+    if t is None or source_key(t["sources"]) != t["sha256"]:
         return None
     fetch = t["fetch_kib"] * COPY_KIB / t["copy_fetch_kib"]
     write = t["write_kib"] * COPY_KIB / t["copy_write_kib"]
