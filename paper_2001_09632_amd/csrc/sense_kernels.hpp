@@ -55,6 +55,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense16(const ImgDev* __restr
   wave_lds_sync();
 #pragma unroll
   for (int b0 = 0; b0 < kTileBlocks; b0 += 2) {
+    if (b0 >= tl.count) break;  // a short tile (image edge, launch split) ends early
     f32x4 C[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
   u32x4 v[kTileBlocks];
 #pragma unroll
   for (int b = 0; b < kTileBlocks; ++b) {
-    const int kk = __builtin_amdgcn_readlane(io.k, b);
+    const int kk = __builtin_amdgcn_readlane(io.k, b);  // 0 past the tile's end
     const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(io.rel_lo, b);
     const uint32_t voff = 4 * lane < kk ? rel4 + 16u * (uint32_t)lane : 0xffffffffu;
     v[b] = __builtin_amdgcn_raw_buffer_load_b128(io.y, voff, 0, 0);
@@ -148,6 +149,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct16(const ImgDev* _
   float* buf1 = lds[wave_in_group()][1].c;
 #pragma unroll
   for (int b = 0; b < kTileBlocks; b += 2) {
+    if (b >= tl.count) break;
     // coefficients of this lane's quad that lie past the block's k
     const int kA = __builtin_amdgcn_readlane(io.k, b);
     const int kB = __builtin_amdgcn_readlane(io.k, b + 1);
@@ -212,8 +214,10 @@ struct EncodeLds {
   PxStage stage[kWavesPerGroup];
 };
 
-// One wave's tile (see k_encode16).
-template <int XF>
+// One wave's tile (see k_encode16).  FULL: the tile holds kTileBlocks
+// blocks, so the loop runs straight through (a separate instantiation: the
+// early exit a shorter tile needs costs the full one about 4 %).
+template <int XF, bool FULL = false>
 __device__ __forceinline__ void encode16_tile(const ImgDev& im, const Tile& tl, const uint8_t* __restrict__ px,
                                               const int32_t* __restrict__ k_all,
                                               const int64_t* __restrict__ off_all, float* __restrict__ y,
@@ -249,8 +253,9 @@ __device__ __forceinline__ void encode16_tile(const ImgDev& im, const Tile& tl, 
   f32x4 C[2] = {forward(0), forward(1)};
 #pragma unroll
   for (int b0 = 0; b0 < kTileBlocks; b0 += 2) {
+    if (!FULL && b0 >= tl.count) break;  // a short tile (image edge, launch split) ends early
     f32x4 Cn[2] = {C[0], C[1]};
-    if (b0 + 2 < kTileBlocks) {
+    if (b0 + 2 < kTileBlocks && (FULL || b0 + 2 < tl.count)) {
       Cn[0] = forward(b0 + 2);
       Cn[1] = forward(b0 + 3);
     }
@@ -317,7 +322,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_encode16(const ImgDev* __rest
   if (wave >= (ntiles << split)) return;
   const Tile tl = split_tile(tiles, wave, split, 16);
   if (tl.count == 0) return;
-  encode16_tile<XF>(imgs[tl.img], tl, px, k_all, off_all, y, out, el);
+  if (tl.count == kTileBlocks)
+    encode16_tile<XF, true>(imgs[tl.img], tl, px, k_all, off_all, y, out, el);
+  else
+    encode16_tile<XF, false>(imgs[tl.img], tl, px, k_all, off_all, y, out, el);
 }
 
 }  // namespace abcs
