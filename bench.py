@@ -114,9 +114,9 @@ COPY_KIB = 1048576.0
 TRAFFIC = {
     "sense_decode": dict(
         sources=("csrc/common.hpp", "csrc/transform16.hpp", "csrc/sense_kernels.hpp"),
-        sha256="e4e3b4f8c856df083b4362b811fe0d93d072a27197fb440021112d39b6dd4d0c",
-        fetch_kib=59281.19, write_kib=840652.0,
-        copy_fetch_kib=524301.24, copy_write_kib=1048576.0),
+        sha256="8828831b9f2d6968bbf6a0f2a5498a69fe2a1d1ecfdfe29886d445d4a7b577b1",
+        fetch_kib=58659.36, write_kib=840664.77,
+        copy_fetch_kib=524301.16, copy_write_kib=1048576.0),
 }
 
 
