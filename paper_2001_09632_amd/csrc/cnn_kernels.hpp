@@ -345,9 +345,6 @@ __global__ __launch_bounds__(256) void k_cnn_last(const ImgDev* __restrict__ img
   }
 }
 
-// Fallback selection: sig_fb[i] = sigma[i] when image i's network output holds
-// a non-finite value, NaN otherwise (NaN makes the BM3D kernels skip the
-// image).  bad[] must be zero on entry.
 // Fallback gate of the learned denoisers (int32[1 + n], zero on entry):
 // gate[1 + i] = 1 for an image whose network output holds a non-finite
 // value, gate[0] = 1 when any image is flagged.
@@ -361,8 +358,8 @@ __global__ __launch_bounds__(256) void k_cnn_check(const int32_t* __restrict__ p
   }
 }
 
-// Flags every image whose noise level lies outside the range the network was
-// trained on, range[0] <= sigma <= range[1] (a NaN sigma is outside).
+// Flags every image whose noise level lies outside the range the network
+// accepts, range[0] <= sigma <= range[1] (a NaN sigma is outside).
 __global__ void k_cnn_sigma_gate(const float* __restrict__ sigma, int n, const float* __restrict__ range,
                                  int32_t* __restrict__ gate) {
   const int i = blockIdx.x * 256 + threadIdx.x;
