@@ -163,6 +163,9 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
   using namespace cnn;
   constexpr int TH = kTileH + 2, TW = kTileW + 2;
   __shared__ __attribute__((aligned(16))) unsigned short tile[TH * TW * kPxStride];
+  // the tile's outputs, so that each pixel's 64 channels leave in one
+  // 128-byte line (two waves hold its two halves)
+  __shared__ __attribute__((aligned(16))) unsigned short obuf[kTileH * kTileW * kPxStride];
   const int wave = wave_in_group();
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
   const int cbase = (wave & 1) * 32;   // output channels of this wave
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const int y = tl.y0 + rbase + r2 + r, x = tl.x0 + n;
-        const int64_t pix = im.out_off + (int64_t)y * im.Wc + x;
+        const int64_t pix = im.out_off + (int64_t)y * im.Wc + x;  // (the mask's pixel, MODE 1)
 #pragma unroll
         for (int cg = 0; cg < 2; ++cg) {
           const int c0 = cbase + 16 * cg + 4 * g;
@@ -260,9 +263,16 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
           uint2 pk;
           pk.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
           pk.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
-          *(uint2*)(out + pix * kCh + c0) = pk;
+          *(uint2*)(obuf + ((rbase + r2 + r) * kTileW + n) * kPxStride + c0) = pk;
         }
       }
+    }
+    __syncthreads();  // every wave's outputs are in obuf
+    for (int t = threadIdx.x; t < kTileH * kTileW * 8; t += 256) {
+      const int px = t >> 3, part = t & 7;
+      const int y = tl.y0 + px / kTileW, x = tl.x0 + px % kTileW;
+      *(u16x8*)(out + (im.out_off + (int64_t)y * im.Wc + x) * kCh + part * 8) =
+          *(const u16x8*)(obuf + px * kPxStride + part * 8);
     }
   }
 }
