@@ -256,7 +256,8 @@ int abcs_sense_decode(const abcs_plan* plan, const uint8_t* d_px, int64_t px_byt
  * the size class of a launch being that of its tile count: 0 below 256
  * tiles, 1 below 2048, 2 below 16384, 3 above (Walsh-Hadamard launches are
  * float32 and use the ABCS_FP32 entry).  All splits are 0 until a table is
- * set; the table is global to the process and read by every launch of
+ * set (the Python binding sets the table measured for this build, if one is
+ * stored); the table is global to the process and read by every launch of
  * abcs_sense, abcs_reconstruct, abcs_sense_decode and abcs_encode. */
 typedef struct abcs_launch_entry {
   int32_t block;       /* 8, 16 or 32 */

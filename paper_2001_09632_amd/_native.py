@@ -132,8 +132,33 @@ def lib():
                         "abcs_encode_workspace_bytes", "abcs_build_id"):
             f.restype = ctypes.c_int
     L.abcs_build_id.restype = ctypes.c_char_p
+    _install_tuned_launches(L)
     _lib = L
     return L
+
+
+TUNED_PATH = os.path.join(_PKG, "tuned_launch.json")
+_TRANSFORMS = {"dct": 0, "wht": 1}
+_PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp16x3": 2, "bf16": 3, "fp16": 4}
+
+
+def _install_tuned_launches(L):
+    """Install the launch splits measured for this build (tune.py), if the
+    stored table belongs to it; otherwise every split stays 0."""
+    import json
+    try:
+        with open(TUNED_PATH) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        return
+    if table.get("build_id") != L.abcs_build_id().decode():
+        return
+    ents = [e for e in table.get("entries", []) if e.get("split", 0) != 0]
+    arr = (LaunchEntry * max(1, len(ents)))()
+    for i, e in enumerate(ents):
+        arr[i] = LaunchEntry(int(e["block"]), _TRANSFORMS[e["transform"]], _PRECISIONS[e["precision"]],
+                             int(e["size_class"]), int(e["split"]))
+    L.abcs_set_launch_table(arr, len(ents))
 
 
 def check(status):

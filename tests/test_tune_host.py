@@ -78,3 +78,18 @@ def test_smooth_images_are_seeded():
     b = tune.smooth_images(2, 64)
     assert a.dtype == np.uint8 and a.shape == (2, 64, 64) and np.array_equal(a, b)
     assert a.std() > 10
+
+
+def test_binding_installs_the_stored_table_of_its_build(g, tmp_path, monkeypatch):
+    """Loading the library installs tuned_launch.json when it belongs to
+    this build, and ignores it otherwise."""
+    from paper_2001_09632_amd import _native
+    e = dict(block=32, transform="dct", precision="bf16", size_class=2, split=2, ms=[1.0, 0.9, 0.8])
+    p = tmp_path / "tuned.json"
+    monkeypatch.setattr(_native, "TUNED_PATH", str(p))
+    p.write_text(json.dumps({"build_id": "another-build", "entries": [e]}))
+    _native._install_tuned_launches(_native.lib())
+    assert g.launch_split(32, "dct", "bf16", 2) == 0
+    p.write_text(json.dumps({"build_id": g.build_id(), "entries": [e]}))
+    _native._install_tuned_launches(_native.lib())
+    assert g.launch_split(32, "dct", "bf16", 2) == 2
