@@ -12,14 +12,16 @@
  *    memory.
  *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
  *    that takes a stream only enqueues work on it and returns without waiting
- *    for the device.
+ *    for the device (abcs_time_splits, the launch tuner's measurement, is the
+ *    one exception).
  *  - Every call returns an abcs_status.  Arguments are checked on the host
  *    before anything is enqueued; on an error return no device memory has
  *    been written and abcs_last_error() describes the problem.  A failed HIP
  *    launch returns ABCS_EHIP.  Nothing throws or aborts across this ABI.
  *  - Thread safety: plans are immutable after creation and may be used from
  *    several host threads; calls that overlap on the device must not share
- *    output buffers.
+ *    output buffers.  The launch table (abcs_set_launch_table) is one per
+ *    process.
  *
  * Geometry (eq 20; Alg 1 and Alg 2 step 1): an H x W image is cropped to
  * H' = B floor(H/B) rows and W' = B floor(W/B) columns and cut into
