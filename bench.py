@@ -114,7 +114,7 @@ COPY_KIB = 1048576.0
 TRAFFIC = {
     "sense_decode": dict(
         sources=("csrc/common.hpp", "csrc/transform16.hpp", "csrc/sense_kernels.hpp"),
-        sha256="8828831b9f2d6968bbf6a0f2a5498a69fe2a1d1ecfdfe29886d445d4a7b577b1",
+        sha256="483e6c1db67f08440ef91c064a4a119924d70ce8304cbbf03f00866165ae9e5c",
         fetch_kib=58659.36, write_kib=840664.77,
         copy_fetch_kib=524301.16, copy_write_kib=1048576.0),
 }
@@ -125,18 +125,19 @@ TRAFFIC = {
 # instruction, FMA = 2 flops; an upper bound, masked lanes count); keyed like
 # TRAFFIC by the sources that define the kernels.
 BM3D_FP32 = dict(sources=("csrc/bm3d_kernels.hpp",),
-                 sha256="c80b853ef68f0b13700bfe76ba2726cd8650924277379dbcea376c0f3bca4f93", flop_per_call=5.41e11)
+                 sha256="c374beb06b2ce67cc8779ca2fd4363525e0c2c02c5ad3490ccd4c12ec01ee376", flop_per_call=5.41e11)
 FP32_PEAK_TFLOPS = 157.3
 
 
 def source_key(sources):
-    """SHA-256 of the files that define a kernel and of the compiler flags."""
+    """SHA-256 of the code of the files that define a kernel (comments aside)
+    and of the compiler flags."""
     import hashlib
     from paper_2001_09632_amd import build
     h = hashlib.sha256(" ".join(build.FLAGS).encode())
     for f in sources:
         with open(os.path.join(ROOT, "paper_2001_09632_amd", f), "rb") as fh:
-            h.update(fh.read())
+            h.update(build.code_text(fh.read()))
     return h.hexdigest()
 
 

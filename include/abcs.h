@@ -244,7 +244,12 @@ int abcs_encode(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, in
                 int64_t* d_offsets, int32_t* d_stat, float* d_y, float* d_out, int precision, void* d_ws,
                 size_t ws_bytes, void* stream);
 /* The second half of abcs_encode on its own (budgets already in d_k and
- * d_offsets): abcs_sense and the decoder's image in d_out (not NULL). */
+ * d_offsets): abcs_sense and the decoder's image in d_out (not NULL).  Each
+ * tile is sensed and decoded in one pass (the coefficients stay in registers
+ * between the forward and the masked inverse transform) for B = 8 and 32 in
+ * every precision and B = 16 in ABCS_FP32; B = 16 in a 16-bit mode runs the
+ * two kernels of abcs_sense and abcs_reconstruct.  Results equal those two
+ * calls' bit for bit. */
 int abcs_sense_decode(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, const int32_t* d_k,
                       const int64_t* d_offsets, float* d_y, float* d_out, int precision, void* stream);
 
@@ -285,8 +290,9 @@ int abcs_plan_size_class(const abcs_plan* plan, int block, int transform);
 int abcs_time_splits(const abcs_plan* plan, const uint8_t* d_px, int64_t px_bytes, const int32_t* d_k,
                      const int64_t* d_offsets, float* d_y, float* d_out, int precision, int reps, float* h_ms,
                      void* stream);
-/* Identity of this build: a hash of the library's sources and compiler
- * flags, under which tuning results are stored. */
+/* Identity of this build: a hash of the library's sources (their code,
+ * comments left out) and compiler flags, under which tuning results are
+ * stored. */
 const char* abcs_build_id(void);
 
 /* IDA post-processing (Section VI; eqs 13, 15, 25, 28; Fig 6).

@@ -636,6 +636,98 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* _
   }
 }
 
+// Sensing and the local decoder in one pass (B = 32): the forward
+// transform's output layout C[i][j][r] = C(16i + 4g + r, 16j + n) is the
+// inverse's input layout, so the decoder takes the block's coefficients
+// from registers, masked past k_i by zigzag rank; only y goes through LDS.
+// Same bits as k_sense32 followed by k_reconstruct32.
+template <int XF, int P = kPrecFP32>
+__global__ __launch_bounds__(kGroupThreads) void k_encode32(const ImgDev* __restrict__ imgs,
+                                                           const Tile* __restrict__ tiles, int ntiles, int split,
+                                                           const uint8_t* __restrict__ px,
+                                                           const int32_t* __restrict__ k_all,
+                                                           const int64_t* __restrict__ off_all,
+                                                           float* __restrict__ y, float* __restrict__ out) {
+  typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+  __shared__ WaveLds32 lds[kWavesPerGroup];
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= (ntiles << split)) return;
+  const Tile tl = split_tile(tiles, wave, split, 32);
+  if (tl.count == 0) return;
+  const ImgDev im = imgs[tl.img];
+  Lane32 L;
+  lane32_init<XF>(L);
+  Lane32P<P> H;
+  if constexpr (P != kPrecFP32) lane32p_init<P>(H, L);
+  const int lane = threadIdx.x & 63;
+  int zr[2][2][4];  // zigzag rank of coefficient (16i + 4g + r, 16j + n)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zr[i][j][r] = c_zzrank32[(16 * i + 4 * L.g + r) * 32 + 16 * j + L.n];
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, 31 * im.pitch + 32 * tl.count);
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(y + im.meas_off, (int)(4 * im.n_meas));
+  const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(off_all + im.blk_off + tl.first, 8 * tl.count);
+  const __amdgpu_buffer_rsrc_t rout = make_rsrc(out + tl.out_base, 4 * (31 * im.Wc + 32 * tl.count));
+  const int32_t kl = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rk, 4 * lane, 0, 0);
+  const int32_t rl = (int32_t)(__builtin_amdgcn_raw_buffer_load_b32(ro, 8 * lane, 0, 0) - (uint32_t)im.meas_off);
+  float* buf = lds[wave_in_group()].c;
+  for (int b = 0; b < tl.count; ++b) {
+    float x[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const uint32_t w =
+            __builtin_amdgcn_raw_buffer_load_b32(rp, (16 * i + L.n) * im.pitch + 32 * b + 16 * k + 4 * L.g, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[i][k][c] = (float)((w >> (8 * c)) & 0xffu);
+      }
+    f32x4 C[2][2];
+    if constexpr (P == kPrecFP32)
+      dct32_fwd(x, L, C);
+    else
+      dct32_fwd_p<P>(x, H, C);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) buf[zr[i][j][r]] = C[i][j][r];
+    wave_lds_sync();
+    const int kk = __builtin_amdgcn_readlane(kl, b);
+    const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(rl, b);
+    for (int q = 0; q < 16 && 64 * q < kk; ++q) {
+      const int z = lane + 64 * q;
+      const uint32_t voff = z < kk ? rel4 + 4u * (uint32_t)z : 0xffffffffu;
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(buf[z]), ry, voff, 0, 0);
+    }
+    wave_lds_sync();
+    float e[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) e[i][j][r] = zr[i][j][r] < kk ? C[i][j][r] : 0.f;
+    f32x4 X[2][2];
+    if constexpr (P == kPrecFP32)
+      idct32_inv(e, L, X);
+    else
+      idct32_inv_p<P>(e, H, X);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const uint32_t off = 4u * (uint32_t)((16 * j + L.n) * im.Wc + 32 * b + 16 * i + 4 * L.g);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X[i][j]), rout, off, 0, kStoreNT);
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // B = 8 on the float32 matrix cores.  Four consecutive blocks b0 .. b0 + 3 of
 // a tile are placed as the quadrants of a 16x16 array (block b0 + 2p + q at
@@ -782,6 +874,86 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct8(const ImgDev* __
     else
       X = idct16_inv_p<P>(e, H);
     const int bx = b0 + xq;
+    const uint32_t off = bx < tl.count ? 4u * (uint32_t)(xrow * im.Wc + 8 * bx + xcol) : 0xffffffffu;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X), rout, off, 0, kStoreNT);
+  }
+}
+
+// Sensing and the local decoder in one pass (B = 8): the forward output
+// C16[4g + r][n] is the inverse's operand layout, so the decoder takes each
+// block's coefficients from registers, masked past its k by zigzag rank (a
+// lane's block is b0 + 2 (g / 2) + n / 8).  Same bits as k_sense8 followed
+// by k_reconstruct8.
+template <int XF, int P = kPrecFP32>
+__global__ __launch_bounds__(kGroupThreads) void k_encode8(const ImgDev* __restrict__ imgs,
+                                                          const Tile* __restrict__ tiles, int ntiles, int split,
+                                                          const uint8_t* __restrict__ px,
+                                                          const int32_t* __restrict__ k_all,
+                                                          const int64_t* __restrict__ off_all,
+                                                          float* __restrict__ y, float* __restrict__ out) {
+  typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+  __shared__ WaveLds8 lds[kWavesPerGroup];
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= (ntiles << split)) return;
+  const Tile tl = split_tile(tiles, wave, split, 8);
+  if (tl.count == 0) return;
+  const ImgDev im = imgs[tl.img];
+  Lane16 L;
+  lane8x4_init<XF>(L);
+  Lane16P<P> H;  // the block-diagonal basis split for the 16-bit modes
+  if constexpr (P != kPrecFP32) lane16p_init<P>(H, L);
+  const int lane = threadIdx.x & 63;
+  // operand side: block quadrant and pixel row / column of this lane
+  const int xq = 2 * (L.n >> 3) + (L.g >> 1), xrow = L.n & 7, xcol = 4 * (L.g & 1);
+  // output side: block quadrant and zigzag rank of coefficient r
+  const int oq = 2 * (L.g >> 1) + (L.n >> 3);
+  int zr[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) zr[r] = c_zzrank8[(4 * (L.g & 1) + r) * 8 + (L.n & 7)];
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, 7 * im.pitch + 8 * tl.count);
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(y + im.meas_off, (int)(4 * im.n_meas));
+  const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(off_all + im.blk_off + tl.first, 8 * tl.count);
+  const __amdgpu_buffer_rsrc_t rout = make_rsrc(out + tl.out_base, 4 * (7 * im.Wc + 8 * tl.count));
+  const int32_t kl = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rk, 4 * lane, 0, 0);
+  const int32_t rl = (int32_t)(__builtin_amdgcn_raw_buffer_load_b32(ro, 8 * lane, 0, 0) - (uint32_t)im.meas_off);
+  WaveLds8& buf = lds[wave_in_group()];
+  for (int b0 = 0; b0 < tl.count; b0 += 4) {
+    const int bx = b0 + xq;
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(
+        rp, bx < tl.count ? (uint32_t)(xrow * im.pitch + 8 * bx + xcol) : 0xffffffffu, 0, 0);
+    float a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = (float)((w >> (8 * c)) & 0xffu);
+    f32x4 C;
+    if constexpr (P == kPrecFP32)
+      C = dct16_fwd(a, L);
+    else
+      C = dct16_fwd_p<P>(a, H);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) buf.c[oq][zr[r]] = C[r];
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = b0 + q;
+      if (b < tl.count) {
+        const int kk = __builtin_amdgcn_readlane(kl, b);
+        const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(rl, b);
+        const uint32_t voff = lane < kk ? rel4 + 4u * (uint32_t)lane : 0xffffffffu;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(buf.c[q][lane]), ry, voff, 0, 0);
+      }
+    }
+    wave_lds_sync();
+    // k of this lane's output block (0 past the tile's end: kl reads 0 there)
+    const int ko = __shfl(kl, (b0 + oq) & 63, 64);
+    float e[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) e[c] = zr[c] < ko ? C[c] : 0.f;
+    f32x4 X;
+    if constexpr (P == kPrecFP32)
+      X = idct16_inv(e, L);
+    else
+      X = idct16_inv_p<P>(e, H);
     const uint32_t off = bx < tl.count ? 4u * (uint32_t)(xrow * im.Wc + 8 * bx + xcol) : 0xffffffffu;
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X), rout, off, 0, kStoreNT);
   }

@@ -8,7 +8,7 @@ precision) and size class this module times abcs_sense_decode on a batch of
 that size at each split (abcs_time_splits), keeps the fastest (split 0 unless
 another one is faster by more than TIE), and stores the table in
 tuned_launch.json next to the library, under the library's build id (a hash of
-its sources and compiler flags).  The binding installs that table when it
+its sources' code, comments left out, and compiler flags).  The binding installs that table when it
 loads the library; a table stored under another build id is never used: any
 change to the kernels or flags asks for a new tuning run.
 

@@ -36,7 +36,7 @@ def _same(a, b):
         assert x.shape == y.shape and np.array_equal(x, y, equal_nan=True), name
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3", "bf16", "fp16"])
 def test_encode_equals_separate_calls(precision):
     px, ent = _entries()
     a = Run(px, ent)

@@ -49,6 +49,17 @@ def test_build_id_is_the_hash_of_the_sources():
     assert g.build_id() == build.build_id()
 
 
+def test_code_text_drops_comments_only():
+    from paper_2001_09632_amd.build import code_text
+    src = (b'int a = 1; // one\n/* two\n   lines */ const char* s = "x // y /* z */";\n'
+           b"char q = '\"'; char e = '\\''; /* c */ int b; \n\n  \n#define M(x) (x) // m\n")
+    assert code_text(src) == (b'int a = 1;\n  const char* s = "x // y /* z */";\n'
+                              b"char q = '\"'; char e = '\\'';   int b;\n#define M(x) (x)")
+    # a changed token changes the text; a changed comment does not
+    assert code_text(src.replace(b"int b", b"int c")) != code_text(src)
+    assert code_text(src.replace(b"two", b"three")) == code_text(src)
+
+
 def test_stored_table_of_another_build_is_ignored(g, tmp_path):
     from paper_2001_09632_amd import tune
     e = dict(block=16, transform="dct", precision="fp32", size_class=3, split=1, ms=[1.0, 0.5, 0.6])
