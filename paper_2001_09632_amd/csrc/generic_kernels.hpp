@@ -306,9 +306,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_gen_ida_step(const ImgDev* __
 //   forward  T_ij = sum_k X_ik D_jk^T,        C_ij = sum_k D_ik T_kj
 //   inverse  Q_ij = sum_k C_ki^T D_kj,   (X^T)_ij = sum_k D_ki^T Q_kj
 // 32 products per stage (64 per block), one wavefront per tile of up to 16
-// blocks, taken one after the other.  Lane (g, n) keeps the basis tiles in
-// both operand layouts: dR[a][b][c] = D[16a + n][16b + 4g + c] and
-// dT[a][b][c] = D[16a + 4g + c][16b + n].
+// blocks, taken one after the other.  For the 16-bit modes lane (g, n) keeps
+// the basis tiles in both operand layouts: dR[a][b][c] = D[16a + n][16b + 4g
+// + c] and dT[a][b][c] = D[16a + 4g + c][16b + n]; float32 uses the truncated
+// layout of Lane32T below.
 // ---------------------------------------------------------------------------
 struct Lane32 {
   int g, n;
@@ -332,18 +333,83 @@ __device__ __forceinline__ void lane32_init(Lane32& L) {
       }
 }
 
-// x[i][k][c] = X[16i + n][16k + 4g + c]  ->  C[i][j][r] = C[16i + 4g + r][16j + n]
-__device__ __forceinline__ void dct32_fwd(const float x[2][2][4], const Lane32& L, f32x4 C[2][2]) {
+// Float32 B = 32 transforms of zigzag-truncated blocks.  As in the 16x16
+// truncated inverse, the inverse's products take four consecutive
+// frequencies each: the K slots of product (k, c) are coefficient rows (first
+// stage) or rows of Q (second stage) 16k + 4c .. 16k + 4c + 3, so a block with
+// k_i coefficients, non-zero only on anti-diagonals u + v <= d (d that of
+// zigzag rank k_i - 1), needs the first-stage product (k, c) of output tile
+// column i only when 16 (k + i) + 4c <= d and the second-stage product (k, c)
+// only when 16k + 4c <= d; the skipped ones would add exact zeros.  The
+// forward transform leaves its output in that layout by taking the basis rows
+// in the order s(n) = 4 (n % 4) + n / 4 within each 16-row half (only rows
+// and columns of the products move: every output is summed over the same K
+// slots in the same order as without the permutation), and it computes only
+// the output tiles that hold a coefficient of zigzag rank below k_i.
+//   forward out C[i][j][r] = C(16i + 4r + g, 16j + s(n));
+//   inverse in  e[k][i][c] = C(16k + 4c + g, 16i + s(n)),
+//           out X[i][j][r] = X[16j + n][16i + 4g + r].
+// Lane (g, n) keeps dS[a][b][c] = D[16a + s(n)][16b + 4g + c] and
+// dP[a][b][c] = D[16a + 4c + g][16b + n].
+struct Lane32T {
+  float dS[2][2][4], dP[2][2][4];
+};
+
+template <int XF>
+__device__ __forceinline__ void lane32t_init(Lane32T& L) {
+  const float* D = GenTables<32, XF>::D();
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, n = lane & 15, sn = 4 * (n & 3) + (n >> 2);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        L.dS[a][b][c] = D[(16 * a + sn) * 32 + 16 * b + 4 * g + c];
+        L.dP[a][b][c] = D[(16 * a + 4 * c + g) * 32 + 16 * b + n];
+      }
+}
+
+// Number of coefficients of a 32x32 block on anti-diagonals below t (the
+// zigzag rank of the first coefficient on diagonal t).
+__host__ __device__ constexpr int zz32_below(int t) {
+  return t <= 32 ? t * (t + 1) / 2 : 1024 - (63 - t) * (64 - t) / 2;
+}
+
+// Zigzag rank of the coefficient that register [a][b][c] of this lane holds:
+// C(16a + 4c + g, 16b + s(n)) in the truncated float32 layout (TRUNC), else
+// C(16a + 4g + c, 16b + n) (the 16-bit modes).
+template <bool TRUNC>
+__device__ __forceinline__ void zz32_ranks(int zr[2][2][4]) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, n = lane & 15, sn = 4 * (n & 3) + (n >> 2);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        zr[a][b][c] = TRUNC ? c_zzrank32[(16 * a + 4 * c + g) * 32 + 16 * b + sn]
+                            : c_zzrank32[(16 * a + 4 * g + c) * 32 + 16 * b + n];
+}
+
+// x[i][k][c] = X[16i + n][16k + 4g + c]; kk (wave-uniform) = the block's
+// k_i.  Output tiles (i, j)
+// with 16 (i + j) past the block's last diagonal are left zero.
+__device__ __forceinline__ void dct32_fwd_t(const float x[2][2][4], const Lane32T& L, int kk, f32x4 C[2][2]) {
   f32x4 T[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       f32x4 t = {0.f, 0.f, 0.f, 0.f};
+      if (kk > zz32_below(16 * j)) {
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+        for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) t = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][k][c], L.dR[j][k][c], t, 0, 0, 0);
+          for (int c = 0; c < 4; ++c) t = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i][k][c], L.dS[j][k][c], t, 0, 0, 0);
+      }
       T[i][j] = t;
     }
 #pragma unroll
@@ -351,16 +417,18 @@ __device__ __forceinline__ void dct32_fwd(const float x[2][2][4], const Lane32& 
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       f32x4 o = {0.f, 0.f, 0.f, 0.f};
+      if (kk > zz32_below(16 * (i + j))) {
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+        for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) o = __builtin_amdgcn_mfma_f32_16x16x4f32(L.dR[i][k][c], T[k][j][c], o, 0, 0, 0);
+          for (int c = 0; c < 4; ++c) o = __builtin_amdgcn_mfma_f32_16x16x4f32(L.dS[i][k][c], T[k][j][c], o, 0, 0, 0);
+      }
       C[i][j] = o;
     }
 }
 
-// e[k][i][c] = C[16k + 4g + c][16i + n]  ->  X[i][j][r] = X[16j + n][16i + 4g + r]
-__device__ __forceinline__ void idct32_inv(const float e[2][2][4], const Lane32& L, f32x4 X[2][2]) {
+// e (zero past the block's kk coefficients) -> X[i][j][r] = X[16j + n][16i + 4g + r]
+__device__ __forceinline__ void idct32_inv_t(const float e[2][2][4], const Lane32T& L, int kk, f32x4 X[2][2]) {
   f32x4 Q[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -370,7 +438,9 @@ __device__ __forceinline__ void idct32_inv(const float e[2][2][4], const Lane32&
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) q = __builtin_amdgcn_mfma_f32_16x16x4f32(e[k][i][c], L.dT[k][j][c], q, 0, 0, 0);
+        for (int c = 0; c < 4; ++c)
+          if (kk > zz32_below(16 * (k + i) + 4 * c))
+            q = __builtin_amdgcn_mfma_f32_16x16x4f32(e[k][i][c], L.dP[k][j][c], q, 0, 0, 0);
       Q[i][j] = q;
     }
 #pragma unroll
@@ -381,7 +451,9 @@ __device__ __forceinline__ void idct32_inv(const float e[2][2][4], const Lane32&
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) o = __builtin_amdgcn_mfma_f32_16x16x4f32(L.dT[k][i][c], Q[k][j][c], o, 0, 0, 0);
+        for (int c = 0; c < 4; ++c)
+          if (kk > zz32_below(16 * k + 4 * c))
+            o = __builtin_amdgcn_mfma_f32_16x16x4f32(L.dP[k][i][c], Q[k][j][c], o, 0, 0, 0);
       X[i][j] = o;
     }
 }
@@ -408,7 +480,8 @@ __device__ __forceinline__ void lane32p_init(Lane32P<P>& H, const Lane32& L) {
     }
 }
 
-// dct32_fwd in precision P (same layouts)
+// x[i][k][c] = X[16i + n][16k + 4g + c] -> C[i][j][r] = C(16i + 4g + r,
+// 16j + n), products in precision P
 template <int P>
 __device__ __forceinline__ void dct32_fwd_p(const float x[2][2][4], const Lane32P<P>& H, f32x4 C[2][2]) {
   constexpr bool BF = Prec16<P>::kBF, SP = Prec16<P>::kSplit;
@@ -450,7 +523,8 @@ __device__ __forceinline__ void dct32_fwd_p(const float x[2][2][4], const Lane32
     }
 }
 
-// idct32_inv in precision P (same layouts)
+// e[k][i][c] = C(16k + 4g + c, 16i + n) -> X[i][j][r] = X[16j + n][16i +
+// 4g + r], products in precision P
 template <int P>
 __device__ __forceinline__ void idct32_inv_p(const float e[2][2][4], const Lane32P<P>& H, f32x4 X[2][2]) {
   constexpr bool BF = Prec16<P>::kBF, SP = Prec16<P>::kSplit;
@@ -499,7 +573,8 @@ struct WaveLds32 {
 
 // y[off_i + z] = C_i[zigzag[z]] for z < k_i (B = 32): the block's
 // coefficients go to LDS at their zigzag rank, then leave in unit-stride
-// stores of k_i values.
+// stores of k_i values (float32: only the output tiles that hold one of them
+// are computed).
 template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restrict__ imgs,
                                                           const Tile* __restrict__ tiles, int ntiles, int split,
@@ -513,18 +588,19 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restr
   const Tile tl = split_tile(tiles, wave, split, 32);
   if (tl.count == 0) return;
   const ImgDev im = imgs[tl.img];
+  constexpr bool TR = (P == kPrecFP32);  // float32: truncated transforms
+  Lane32T LT;
   Lane32 L;
-  lane32_init<XF>(L);
   Lane32P<P> H;
-  if constexpr (P != kPrecFP32) lane32p_init<P>(H, L);
-  const int lane = threadIdx.x & 63;
-  int zr[2][2][4];  // zigzag rank of coefficient (16i + 4g + r, 16j + n)
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) zr[i][j][r] = c_zzrank32[(16 * i + 4 * L.g + r) * 32 + 16 * j + L.n];
+  if constexpr (TR) {
+    lane32t_init<XF>(LT);
+  } else {
+    lane32_init<XF>(L);
+    lane32p_init<P>(H, L);
+  }
+  const int lane = threadIdx.x & 63, lg = lane >> 4, ln = lane & 15;
+  int zr[2][2][4];  // zigzag rank of the coefficient in each output register
+  zz32_ranks<TR>(zr);
   const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, 31 * im.pitch + 32 * tl.count);
   const __amdgpu_buffer_rsrc_t ry = make_rsrc(y + im.meas_off, (int)(4 * im.n_meas));
   const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
@@ -539,13 +615,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restr
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         const uint32_t w =
-            __builtin_amdgcn_raw_buffer_load_b32(rp, (16 * i + L.n) * im.pitch + 32 * b + 16 * k + 4 * L.g, 0, 0);
+            __builtin_amdgcn_raw_buffer_load_b32(rp, (16 * i + ln) * im.pitch + 32 * b + 16 * k + 4 * lg, 0, 0);
 #pragma unroll
         for (int c = 0; c < 4; ++c) x[i][k][c] = (float)((w >> (8 * c)) & 0xffu);
       }
+    const int kk = __builtin_amdgcn_readlane(kl, b);
     f32x4 C[2][2];
-    if constexpr (P == kPrecFP32)
-      dct32_fwd(x, L, C);
+    if constexpr (TR)
+      dct32_fwd_t(x, LT, kk, C);
     else
       dct32_fwd_p<P>(x, H, C);
 #pragma unroll
@@ -555,7 +632,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restr
 #pragma unroll
         for (int r = 0; r < 4; ++r) buf[zr[i][j][r]] = C[i][j][r];
     wave_lds_sync();
-    const int kk = __builtin_amdgcn_readlane(kl, b);
     const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(rl, b);
     for (int q = 0; q < 16 && 64 * q < kk; ++q) {
       const int z = lane + 64 * q;
@@ -568,7 +644,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_sense32(const ImgDev* __restr
 
 // out = D^T C D per block (B = 32), C zero beyond the block's k_i zigzag
 // entries: the block's coefficients are staged in LDS in zigzag order (zero
-// past k_i) and gathered in the inverse's operand layout.
+// past k_i) and gathered in the inverse's operand layout; in float32 the
+// inverse skips the products of all-zero operands.
 template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* __restrict__ imgs,
                                                                 const Tile* __restrict__ tiles, int ntiles, int split,
@@ -583,18 +660,19 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* _
   const Tile tl = split_tile(tiles, wave, split, 32);
   if (tl.count == 0) return;
   const ImgDev im = imgs[tl.img];
+  constexpr bool TR = (P == kPrecFP32);  // float32: truncated transforms
+  Lane32T LT;
   Lane32 L;
-  lane32_init<XF>(L);
   Lane32P<P> H;
-  if constexpr (P != kPrecFP32) lane32p_init<P>(H, L);
-  const int lane = threadIdx.x & 63;
-  int zr[2][2][4];  // zigzag rank of coefficient (16k + 4g + c, 16i + n)
-#pragma unroll
-  for (int k = 0; k < 2; ++k)
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) zr[k][i][c] = c_zzrank32[(16 * k + 4 * L.g + c) * 32 + 16 * i + L.n];
+  if constexpr (TR) {
+    lane32t_init<XF>(LT);
+  } else {
+    lane32_init<XF>(L);
+    lane32p_init<P>(H, L);
+  }
+  const int lane = threadIdx.x & 63, lg = lane >> 4, ln = lane & 15;
+  int zr[2][2][4];  // zigzag rank of the coefficient in each operand register
+  zz32_ranks<TR>(zr);
   const __amdgpu_buffer_rsrc_t ry = make_rsrc(y + im.meas_off, (int)(4 * im.n_meas));
   const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
   const __amdgpu_buffer_rsrc_t ro = make_rsrc(off_all + im.blk_off + tl.first, 8 * tl.count);
@@ -621,8 +699,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* _
         for (int c = 0; c < 4; ++c) e[k][i][c] = buf[zr[k][i][c]];
     wave_lds_sync();
     f32x4 X[2][2];
-    if constexpr (P == kPrecFP32)
-      idct32_inv(e, L, X);
+    if constexpr (TR)
+      idct32_inv_t(e, LT, kk, X);
     else
       idct32_inv_p<P>(e, H, X);
     // X[i][j][r] = pixel (16j + n, 16i + 4g + r)
@@ -630,17 +708,17 @@ __global__ __launch_bounds__(kGroupThreads) void k_reconstruct32(const ImgDev* _
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const uint32_t off = 4u * (uint32_t)((16 * j + L.n) * im.Wc + 32 * b + 16 * i + 4 * L.g);
+        const uint32_t off = 4u * (uint32_t)((16 * j + ln) * im.Wc + 32 * b + 16 * i + 4 * lg);
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X[i][j]), rout, off, 0, kStoreNT);
       }
   }
 }
 
 // Sensing and the local decoder in one pass (B = 32): the forward
-// transform's output layout C[i][j][r] = C(16i + 4g + r, 16j + n) is the
-// inverse's input layout, so the decoder takes the block's coefficients
-// from registers, masked past k_i by zigzag rank; only y goes through LDS.
-// Same bits as k_sense32 followed by k_reconstruct32.
+// transform's output layout is the inverse's input layout (the truncated
+// float32 layout, or that of the 16-bit modes), so the decoder takes the
+// block's coefficients from registers, masked past k_i by zigzag rank; only
+// y goes through LDS.  Same bits as k_sense32 followed by k_reconstruct32.
 template <int XF, int P = kPrecFP32>
 __global__ __launch_bounds__(kGroupThreads) void k_encode32(const ImgDev* __restrict__ imgs,
                                                            const Tile* __restrict__ tiles, int ntiles, int split,
@@ -655,18 +733,19 @@ __global__ __launch_bounds__(kGroupThreads) void k_encode32(const ImgDev* __rest
   const Tile tl = split_tile(tiles, wave, split, 32);
   if (tl.count == 0) return;
   const ImgDev im = imgs[tl.img];
+  constexpr bool TR = (P == kPrecFP32);  // float32: truncated transforms
+  Lane32T LT;
   Lane32 L;
-  lane32_init<XF>(L);
   Lane32P<P> H;
-  if constexpr (P != kPrecFP32) lane32p_init<P>(H, L);
-  const int lane = threadIdx.x & 63;
-  int zr[2][2][4];  // zigzag rank of coefficient (16i + 4g + r, 16j + n)
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) zr[i][j][r] = c_zzrank32[(16 * i + 4 * L.g + r) * 32 + 16 * j + L.n];
+  if constexpr (TR) {
+    lane32t_init<XF>(LT);
+  } else {
+    lane32_init<XF>(L);
+    lane32p_init<P>(H, L);
+  }
+  const int lane = threadIdx.x & 63, lg = lane >> 4, ln = lane & 15;
+  int zr[2][2][4];  // zigzag rank of the coefficient in each output register
+  zz32_ranks<TR>(zr);
   const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, 31 * im.pitch + 32 * tl.count);
   const __amdgpu_buffer_rsrc_t ry = make_rsrc(y + im.meas_off, (int)(4 * im.n_meas));
   const __amdgpu_buffer_rsrc_t rk = make_rsrc(k_all + im.blk_off + tl.first, 4 * tl.count);
@@ -682,13 +761,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_encode32(const ImgDev* __rest
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         const uint32_t w =
-            __builtin_amdgcn_raw_buffer_load_b32(rp, (16 * i + L.n) * im.pitch + 32 * b + 16 * k + 4 * L.g, 0, 0);
+            __builtin_amdgcn_raw_buffer_load_b32(rp, (16 * i + ln) * im.pitch + 32 * b + 16 * k + 4 * lg, 0, 0);
 #pragma unroll
         for (int c = 0; c < 4; ++c) x[i][k][c] = (float)((w >> (8 * c)) & 0xffu);
       }
+    const int kk = __builtin_amdgcn_readlane(kl, b);
     f32x4 C[2][2];
-    if constexpr (P == kPrecFP32)
-      dct32_fwd(x, L, C);
+    if constexpr (TR)
+      dct32_fwd_t(x, LT, kk, C);
     else
       dct32_fwd_p<P>(x, H, C);
 #pragma unroll
@@ -698,7 +778,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_encode32(const ImgDev* __rest
 #pragma unroll
         for (int r = 0; r < 4; ++r) buf[zr[i][j][r]] = C[i][j][r];
     wave_lds_sync();
-    const int kk = __builtin_amdgcn_readlane(kl, b);
     const uint32_t rel4 = 4u * (uint32_t)__builtin_amdgcn_readlane(rl, b);
     for (int q = 0; q < 16 && 64 * q < kk; ++q) {
       const int z = lane + 64 * q;
@@ -714,15 +793,15 @@ __global__ __launch_bounds__(kGroupThreads) void k_encode32(const ImgDev* __rest
 #pragma unroll
         for (int r = 0; r < 4; ++r) e[i][j][r] = zr[i][j][r] < kk ? C[i][j][r] : 0.f;
     f32x4 X[2][2];
-    if constexpr (P == kPrecFP32)
-      idct32_inv(e, L, X);
+    if constexpr (TR)
+      idct32_inv_t(e, LT, kk, X);
     else
       idct32_inv_p<P>(e, H, X);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const uint32_t off = 4u * (uint32_t)((16 * j + L.n) * im.Wc + 32 * b + 16 * i + 4 * L.g);
+        const uint32_t off = 4u * (uint32_t)((16 * j + ln) * im.Wc + 32 * b + 16 * i + 4 * lg);
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X[i][j]), rout, off, 0, kStoreNT);
       }
   }
