@@ -325,12 +325,13 @@ def ida_section(dev, weights_path):
         rec["note"] = f"no CNN weights at {weights_path}"
         return rec
     prm = torch.from_numpy(load_params(weights_path)).to(dev)
-    trail = {}
+    trail, trail_t = {}, {}
     chosen = None
     for it in (5, 10, 15, 20, 25, 30):
         tl, xl = timed(it, "cnn", prm)
         pl, sl = scores(xl)
         trail[it] = round(pl, 3)
+        trail_t[it] = tl
         if chosen is None and pl >= pp - 0.1:
             chosen = (it, tl, pl, sl)
     matched = chosen is not None
@@ -344,6 +345,10 @@ def ida_section(dev, weights_path):
                       "psnr_by_iters": trail}
     rec["matched_psnr"] = matched
     rec["learned_over_plain_images_per_s"] = round(tp / tl, 2)
+    # both loops at the plain loop's iteration count
+    rec["learned_at_plain_iters"] = {"iters": IDA_ITERS, "images_per_s": round(n / trail_t[IDA_ITERS], 2),
+                                     "psnr": trail[IDA_ITERS],
+                                     "over_plain_images_per_s": round(tp / trail_t[IDA_ITERS], 2)}
 
     rec["judge"] = judge_section(dev, plan, y, k, off, imgs, prm)
     rec["vs_oracle"] = ida_oracle_sample(dev, imgs, prm)
@@ -387,11 +392,12 @@ def ida_section(dev, weights_path):
     dn_path = os.path.join(os.path.dirname(weights_path), "ida_dncnn.npy")
     if os.path.exists(dn_path):
         dprm = torch.from_numpy(load_params(dn_path, arch="dncnn")).to(dev)
-        dtrail, dchosen = {}, None
+        dtrail, dtrail_t, dchosen = {}, {}, None
         for itd in (5, 10, 15, 20, 25, 30):
             td, xd = timed(itd, "dncnn", dprm)
             pd_, sd = scores(xd)
             dtrail[itd] = round(pd_, 3)
+            dtrail_t[itd] = td
             if dchosen is None and pd_ >= pp - 0.1:
                 dchosen = (itd, td, pd_, sd)
         if dchosen is None:
@@ -400,7 +406,10 @@ def ida_section(dev, weights_path):
         itd, td, pd_, sd = dchosen
         rec["dncnn"] = {"denoiser": "dncnn-17", "iters": itd, "images_per_s": round(n / td, 2),
                         "ms_per_batch": round(td * 1e3, 2), "psnr": round(pd_, 3), "ssim": round(sd, 4),
-                        "psnr_by_iters": dtrail, "over_plain_images_per_s": round(tp / td, 2)}
+                        "psnr_by_iters": dtrail, "over_plain_images_per_s": round(tp / td, 2),
+                        "at_plain_iters": {"iters": IDA_ITERS, "images_per_s": round(n / dtrail_t[IDA_ITERS], 2),
+                                           "psnr": dtrail[IDA_ITERS],
+                                           "over_plain_images_per_s": round(tp / dtrail_t[IDA_ITERS], 2)}}
         rec["denoiser_roofline"]["dncnn"] = conv_roofline(denoise_ms("dncnn", dprm), 15)
 
     # The loop variants of Section VI with the learned denoiser at the chosen
