@@ -65,85 +65,6 @@ __global__ __launch_bounds__(256) void k_cnn_prep(const float* __restrict__ blob
   if (i < 9 * 64) w8r[i] = bf2f(f2bf(blob[kW8 + i]));
 }
 
-// Layer 1 (2 -> 64) on float32 MFMA (v_mfma_f32_16x16x4_f32); a workgroup
-// loops over 8 x 16-pixel tiles.  K = 18 = 9 taps x 2 input channels (padded to 20), in
-// the order k = 2 tap + c; input channel 0 is v / 255, channel 1 the constant
-// map min(sigma, 255) / 255 (both zero outside the image).  Wave w computes
-// rows 2w, 2w + 1: for 16 output channels x 16 pixels a product has the
-// weights as A (lane (g, n): channel n, k = 4 chunk + g) and the inputs as B.
-// The outputs go through LDS so that each pixel's 64 channels (128 bytes)
-// leave in whole-line stores.
-__global__ __launch_bounds__(256) void k_cnn_first(const ImgDev* __restrict__ imgs, const CnnTile* __restrict__ tiles,
-                                                  int ntiles, const float* __restrict__ v,
-                                                  const float* __restrict__ sigma, const float* __restrict__ w1r,
-                                                  const float* __restrict__ b1, unsigned short* __restrict__ act) {
-  using namespace cnn;
-  constexpr int TH = kTileH + 2, TW = kTileW + 2;
-  constexpr int kOutStride = kCh + 8;  // bf16 per staged output pixel
-  __shared__ float vin[TH * TW];
-  __shared__ __attribute__((aligned(16))) unsigned short obuf[kTileH * kTileW * kOutStride];
-  __shared__ float sb[kCh];
-  if (threadIdx.x < kCh) sb[threadIdx.x] = b1[threadIdx.x];
-  const int wave = wave_in_group();
-  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
-  // A: weight of output channel 16 cg + n at k = 4 c + g
-  float wa[4][5];
-#pragma unroll
-  for (int cg = 0; cg < 4; ++cg)
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      const int k = 4 * c + g;
-      wa[cg][c] = k < 18 ? w1r[(16 * cg + n) * 18 + k] : 0.f;
-    }
-  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
-    const CnnTile tl = tiles[ti];
-    const ImgDev im = imgs[tl.img];
-    const float sg = fminf(sigma[tl.img], 255.f) * (1.f / 255.f);
-    __syncthreads();  // previous tile's outputs stored
-    for (int t = threadIdx.x; t < TH * TW; t += 256) {
-      const int ty = t / TW, tx = t - ty * TW;
-      const int y = tl.y0 + ty - 1, x = tl.x0 + tx - 1;
-      vin[t] = ((unsigned)y < (unsigned)im.Hc && (unsigned)x < (unsigned)im.Wc)
-                   ? v[im.out_off + (int64_t)y * im.Wc + x] * (1.f / 255.f)
-                   : 0.f;
-    }
-    __syncthreads();
-  #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int row = 2 * wave + r;
-      float bv[5];
-  #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        const int k = 4 * c + g, tap = k >> 1, ch = k & 1;
-        const int dy = tap / 3, dx = tap % 3;
-        const bool inside = k < 18 && (unsigned)(tl.y0 + row + dy - 1) < (unsigned)im.Hc &&
-                            (unsigned)(tl.x0 + n + dx - 1) < (unsigned)im.Wc;
-        bv[c] = !inside ? 0.f : (ch == 0 ? vin[(row + dy) * TW + n + dx] : sg);
-      }
-  #pragma unroll
-      for (int cg = 0; cg < 4; ++cg) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  #pragma unroll
-        for (int c = 0; c < 5; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[cg][c], bv[c], acc, 0, 0, 0);
-        // acc[q]: channel 16 cg + 4 g + q of pixel (row, n)
-        const int c0 = 16 * cg + 4 * g;
-        uint2 pk;
-        pk.x = (uint32_t)f2bf(fmaxf(acc[0] + sb[c0], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1] + sb[c0 + 1], 0.f)) << 16);
-        pk.y = (uint32_t)f2bf(fmaxf(acc[2] + sb[c0 + 2], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3] + sb[c0 + 3], 0.f)) << 16);
-        *(uint2*)(obuf + (row * kTileW + n) * kOutStride + c0) = pk;
-      }
-    }
-    __syncthreads();
-    // 128 pixels x 8 parts of 16 bytes
-    for (int t = threadIdx.x; t < kTileH * kTileW * 8; t += 256) {
-      const int px = t >> 3, part = t & 7;
-      const int y = tl.y0 + px / kTileW, x = tl.x0 + px % kTileW;
-      *(u16x8*)(act + (im.out_off + (int64_t)y * im.Wc + x) * kCh + part * 8) =
-          *(const u16x8*)(obuf + px * kOutStride + part * 8);
-    }
-  }
-}
-
 // Layers 2..7 (64 -> 64) on bfloat16 MFMA (v_mfma_f32_16x16x32_bf16).  A
 // workgroup computes an 8 x 16-pixel tile: the input tile and its one-pixel
 // halo are staged in LDS (zero outside the image), each wavefront keeps the
@@ -154,22 +75,182 @@ __global__ __launch_bounds__(256) void k_cnn_first(const ImgDev* __restrict__ im
 // MODE 1 (input gradient): weights are the transposed, tap-flipped copy,
 //         out = bf16(sum) where mask > 0 (the ReLU of the layer below), else 0.
 // MODE 2: out = bf16(sum) (the pre-normalisation values of DnCNN's layers).
-template <int MODE>
+//
+// Inference (MODE 0) can take the network's first and last layers in:
+// kCnnInFirst: the layer's input is layer 1's output, computed while the
+//   tile is staged from the network input v (4 bytes per pixel) instead of
+//   read as 64 channels (128 bytes per pixel): for the tile and its halo,
+//   sum over the 9 taps of w1[c][tap][0] v(q) / 255 + w1[c][tap][1] sigma',
+//   on bfloat16 MFMA with every float32 operand split into two bfloat16
+//   halves (v / 255 and sigma' = min(sigma, 255) / 255 as hi + lo, weights
+//   exact in bfloat16), K = 36 of two 16x16x32 products, then
+//   bf16(ReLU(sum + b1)), zero outside the image.
+// kCnnOutTaps: instead of its 64 channels a (bfloat16, as stored), the layer
+//   writes for each pixel q the nine partial sums t_tap(q) = sum_c w8[tap][c]
+//   a_c(q) of the last layer (one 16x16x32 product per row: taps as A rows,
+//   a wave's 32 channels as K; the two halves of the channels added in
+//   float32), 36 bytes per pixel in nine planes of the plan's pixels, and
+//   k_cnn_taps_out adds them up: out(p) = v(p) - 255 (b8 + sum_tap
+//   t_tap(p + offset_tap)).
+// kCnnKeep (training): kCnnInFirst also writes layer 1's output of the tile
+//   to fz.keep, kCnnOutTaps also writes the layer's own output to `out`, so
+//   that the backward pass has every activation; the arithmetic is that of
+//   inference, so a training step's forward output equals abcs_denoise's.
+// kCnnInFirst also serves MODE 2 (DnCNN's training forward).
+constexpr int kCnnInFirst = 1, kCnnOutTaps = 2, kCnnKeep = 4;
+
+// Layer 1 for the staged tile of a middle layer (kCnnInFirst): the tile's
+// (kTileH + 2) x (kTileW + 2) pixels, taken 16 at a time in raster order
+// (wave w takes groups w, w + 4, w + 8), get their 64 channels in `tile`
+// (which has room for the last group's 12 spare pixels, so that every lane
+// stores).  win holds, over the tile with a two-pixel halo, the four
+// bfloat16 K slots of one tap: v / 255 as hi and lo, and sigma' as hi and lo
+// where the pixel lies in the image (all zero outside it); w1s the A
+// operands (channel c, K slot 4 tap + part); sb1 the bias (16-byte aligned).
+// Selections are masks, not branches.
+__device__ __forceinline__ void stage_first_layer(const CnnTile& tl, const ImgDev& im, const uint2* win,
+                                                  const unsigned short* w1s, const float* sb1, unsigned short* tile,
+                                                  int wave, int g, int n) {
+  using namespace cnn;
+  constexpr int TH = kTileH + 2, TW = kTileW + 2, VW = kTileW + 4;
+  constexpr int NPX = TH * TW, NGRP = (NPX + 15) / 16;
+  static_assert(NGRP == 3 * kWavesPerGroup, "three pixel groups per wave");
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int t = 16 * (wave + kWavesPerGroup * i) + n;
+    const bool valid = t < NPX;
+    const int tc = valid ? t : 0;
+    const int ty = tc / TW, tx = tc - ty * TW;
+    // B operands: K slots 32 kc + 8 g .. + 7 are taps 8 kc + 2 g and 8 kc + 2 g + 1
+    uint4 bw[2];
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      uint2 h2[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int tap = 8 * kc + 2 * g + h;
+        const bool use = valid && tap < 9;
+        const int tp = use ? tap : 0;
+        const int dy = tp / 3, dx = tp - 3 * (tp / 3);
+        const uint32_t m = use ? 0xffffffffu : 0u;
+        const uint2 w = win[(ty + dy) * VW + tx + dx];
+        h2[h] = make_uint2(w.x & m, w.y & m);
+      }
+      bw[kc] = make_uint4(h2[0].x, h2[0].y, h2[1].x, h2[1].y);
+    }
+    const int cy = tl.y0 + ty - 1, cx = tl.x0 + tx - 1;
+    const bool inside = valid && (unsigned)cy < (unsigned)im.Hc && (unsigned)cx < (unsigned)im.Wc;
+    const uint32_t keep = inside ? 0xffffffffu : 0u;
+    f32x4 acc[4];
+#pragma unroll
+    for (int cg = 0; cg < 4; ++cg) {
+      acc[cg] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kc = 0; kc < 2; ++kc) {
+        const bf16x8 a = *(const bf16x8*)(w1s + (16 * cg + n) * 64 + 32 * kc + 8 * g);
+        acc[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bw[kc]), acc[cg], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int cg = 0; cg < 4; ++cg) {
+      // acc[cg][q]: channel 16 cg + 4 g + q of pixel t
+      const int c0 = 16 * cg + 4 * g;
+      const float4 bb = *(const float4*)(sb1 + c0);
+      const float bq[4] = {bb.x, bb.y, bb.z, bb.w};
+      uint32_t o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = (uint32_t)f2bf(fmaxf(acc[cg][q] + bq[q], 0.f));
+      uint2 pk;
+      pk.x = (o[0] | (o[1] << 16)) & keep;
+      pk.y = (o[2] | (o[3] << 16)) & keep;
+      *(uint2*)(tile + t * kPxStride + c0) = pk;
+    }
+  }
+}
+
+// out(p) = v(p) - 255 (b8 + sum over taps of t_tap(p + offset_tap)), the
+// planes t_tap written by the last middle layer (kCnnOutTaps), zero outside
+// the image; one thread per pixel, taps in order.  pix_img: the image of
+// each chunk of 2^kPixChunkShift pixels.
+__global__ __launch_bounds__(256) void k_cnn_taps_out(const ImgDev* __restrict__ imgs,
+                                                     const int32_t* __restrict__ pix_img, int64_t pixels,
+                                                     const float* __restrict__ taps, const float* __restrict__ v,
+                                                     const float* __restrict__ b8p, float* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= pixels) return;
+  const ImgDev im = imgs[pix_img[p >> kPixChunkShift]];  // one entry per 64-pixel chunk
+  const int64_t rel = p - im.out_off;
+  const int y = (int)(rel / im.Wc), x = (int)(rel - (int64_t)y * im.Wc);
+  float sum = 0.f;
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+    if ((unsigned)yy < (unsigned)im.Hc && (unsigned)xx < (unsigned)im.Wc)
+      sum += taps[tap * pixels + im.out_off + (int64_t)yy * im.Wc + xx];
+  }
+  out[p] = v[p] - 255.f * (b8p[0] + sum);
+}
+
+struct CnnFuse {
+  const float* v;        // kCnnInFirst: the network input (plan pixels)
+  const float* sigma;    //   per image
+  const float* w1r;      //   layer 1 weights, bfloat16-rounded float32
+  const float* b1;       //   layer 1 bias
+  const float* w8r;      // kCnnOutTaps: layer 8 weights, bfloat16-rounded float32
+  float* taps;           //   nine planes of `plane` floats
+  int64_t plane;
+  unsigned short* keep;  // kCnnInFirst | kCnnKeep: layer 1's output
+};
+
+template <int MODE, int FUSE = 0>
 __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ imgs, const CnnTile* __restrict__ tiles,
                                                 int ntiles, const unsigned short* __restrict__ in,
                                                 const unsigned short* __restrict__ w, const float* __restrict__ bias,
                                                 const unsigned short* __restrict__ mask,
-                                                unsigned short* __restrict__ out) {
+                                                unsigned short* __restrict__ out, CnnFuse fz) {
   using namespace cnn;
+  constexpr bool FIRST = (FUSE & kCnnInFirst) != 0, TAPS = (FUSE & kCnnOutTaps) != 0;
+  constexpr bool KEEP = (FUSE & kCnnKeep) != 0;
+  static_assert(MODE == 0 || (MODE == 2 && !TAPS) || FUSE == 0, "forward layers only");
   constexpr int TH = kTileH + 2, TW = kTileW + 2;
-  __shared__ __attribute__((aligned(16))) unsigned short tile[TH * TW * kPxStride];
+  // (kCnnInFirst: room for the 12 spare pixels of layer 1's last group)
+  __shared__ __attribute__((aligned(16))) unsigned short tile[(TH * TW + (FIRST ? 12 : 0)) * kPxStride];
   // the tile's outputs, so that each pixel's 64 channels leave in one
   // 128-byte line (two waves hold its two halves)
-  __shared__ __attribute__((aligned(16))) unsigned short obuf[kTileH * kTileW * kPxStride];
+  constexpr bool ACT_OUT = !TAPS || KEEP;
+  __shared__ __attribute__((aligned(16))) unsigned short obuf[ACT_OUT ? kTileH * kTileW * kPxStride : 1];
+  // kCnnOutTaps: the two channel halves' partial sums, [half][row][tap][pixel]
+  __shared__ float tpart[TAPS ? 2 * kTileH * 9 * kTileW : 1];
   const int wave = wave_in_group();
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
   const int cbase = (wave & 1) * 32;   // output channels of this wave
   const int rbase = (wave >> 1) * 4;   // tile rows of this wave
+  // kCnnInFirst: layer 1's B operand slots over the tile and a two-pixel
+  // halo, and its A operands: channel c, K slot 4 tap + part (part 0, 1:
+  // weight of v, 2, 3: weight of sigma'), slots 36..63 zero
+  constexpr int VH = kTileH + 4, VW = kTileW + 4;
+  __shared__ uint2 win[FIRST ? VH * VW : 1];
+  __shared__ __attribute__((aligned(16))) unsigned short w1s[FIRST ? kCh * 64 : 1];
+  __shared__ __attribute__((aligned(16))) float sb1[FIRST ? kCh : 1];
+  if constexpr (FIRST) {
+    for (int t = threadIdx.x; t < kCh * 64; t += 256) {
+      const int c = t >> 6, k = t & 63, tap = k >> 2, part = k & 3;
+      w1s[t] = k < 36 ? f2bf(fz.w1r[c * 18 + 2 * tap + (part >> 1)]) : (unsigned short)0;
+    }
+    if (threadIdx.x < kCh) sb1[threadIdx.x] = fz.b1[threadIdx.x];
+  }
+  // kCnnOutTaps: A operand of the last layer, row n = tap (n < 9), K slot
+  // 8 g + j = channel cbase + 4 g + j (j < 4) or cbase + 16 + 4 g + j - 4
+  bf16x8 w8a;
+  if constexpr (TAPS) {
+    u16x8 t8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = cbase + (j < 4 ? 4 * g + j : 16 + 4 * g + j - 4);
+      t8[j] = n < 9 ? f2bf(fz.w8r[n * kCh + c]) : (unsigned short)0;
+    }
+    w8a = __builtin_bit_cast(bf16x8, t8);
+  }
   // A operands, loaded once per workgroup: weights of output channel
   // cbase + 16 cg + n, K slice (tap, 32 kc + 8 g .. + 8).
   bf16x8 wa[2][9][2];
@@ -184,23 +265,37 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
   if (threadIdx.x < kCh) sbias[threadIdx.x] = MODE == 0 ? bias[threadIdx.x] : 0.f;
 
   // The input tile (with its one-pixel halo, zero outside the image) of the
-  // next tile is loaded into registers while the current one is computed.
-  constexpr int NST = (TH * TW * 8 + 255) / 256;
+  // next tile is loaded into registers while the current one is computed
+  // (kCnnInFirst: v over the tile with a two-pixel halo, one value a thread).
+  constexpr int NST = FIRST ? 1 : (TH * TW * 8 + 255) / 256;
+  static_assert(!FIRST || VH * VW <= 256, "one v value per thread");
   u16x8 pre[NST];
+  float vpre = 0.f, spre = 0.f;
   auto fetch = [&](int tj) {
     const CnnTile tn = tiles[tj];
     const ImgDev imn = imgs[tn.img];
-    // the image's activations; offsets outside it read as zero
-    const __amdgpu_buffer_rsrc_t ra = make_rsrc(in + imn.out_off * kCh, imn.Hc * imn.Wc * kCh * 2);
+    if constexpr (FIRST) {
+      const __amdgpu_buffer_rsrc_t rv = make_rsrc(fz.v + imn.out_off, imn.Hc * imn.Wc * 4);
+      const int t = threadIdx.x;
+      const int ty = t / VW, tx = t - ty * VW;
+      const int y = tn.y0 + ty - 2, x = tn.x0 + tx - 2;
+      const bool ok = t < VH * VW && (unsigned)y < (unsigned)imn.Hc && (unsigned)x < (unsigned)imn.Wc;
+      vpre = __uint_as_float(
+          __builtin_amdgcn_raw_buffer_load_b32(rv, ok ? (uint32_t)((y * imn.Wc + x) * 4) : 0xffffffffu, 0, 0));
+      spre = fz.sigma[tn.img];
+    } else {
+      // the image's activations; offsets outside it read as zero
+      const __amdgpu_buffer_rsrc_t ra = make_rsrc(in + imn.out_off * kCh, imn.Hc * imn.Wc * kCh * 2);
 #pragma unroll
-    for (int sidx = 0; sidx < NST; ++sidx) {
-      const int t = threadIdx.x + 256 * sidx;
-      const int px = t >> 3, part = t & 7;
-      const int ty = px / TW, tx = px - ty * TW;
-      const int y = tn.y0 + ty - 1, x = tn.x0 + tx - 1;
-      const bool ok = t < TH * TW * 8 && (unsigned)y < (unsigned)imn.Hc && (unsigned)x < (unsigned)imn.Wc;
-      const uint32_t off = ok ? (uint32_t)(((y * imn.Wc + x) * kCh + part * 8) * 2) : 0xffffffffu;
-      pre[sidx] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, off, 0, 0));
+      for (int sidx = 0; sidx < NST; ++sidx) {
+        const int t = threadIdx.x + 256 * sidx;
+        const int px = t >> 3, part = t & 7;
+        const int ty = px / TW, tx = px - ty * TW;
+        const int y = tn.y0 + ty - 1, x = tn.x0 + tx - 1;
+        const bool ok = t < TH * TW * 8 && (unsigned)y < (unsigned)imn.Hc && (unsigned)x < (unsigned)imn.Wc;
+        const uint32_t off = ok ? (uint32_t)(((y * imn.Wc + x) * kCh + part * 8) * 2) : 0xffffffffu;
+        pre[sidx] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, off, 0, 0));
+      }
     }
   };
   if ((int)blockIdx.x < ntiles) fetch(blockIdx.x);
@@ -208,13 +303,41 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
     const CnnTile tl = tiles[ti];
     const ImgDev im = imgs[tl.img];
     __syncthreads();  // previous tile fully consumed
+    if constexpr (FIRST) {
+      if (threadIdx.x < VH * VW) {
+        // the K slots of this window pixel: v / 255 (zero outside the image:
+        // the load above reads zero there) and sigma' where inside
+        const int ty = threadIdx.x / VW, tx = threadIdx.x - ty * VW;
+        const int y = tl.y0 + ty - 2, x = tl.x0 + tx - 2;
+        const bool in_img = (unsigned)y < (unsigned)im.Hc && (unsigned)x < (unsigned)im.Wc;
+        const float sg = fminf(spre, 255.f) * (1.f / 255.f);
+        const unsigned short sh = f2bf(sg), sl = f2bf(sg - bf2f(sh));
+        const float xv = vpre * (1.f / 255.f);
+        const unsigned short vh = f2bf(xv), vl = f2bf(xv - bf2f(vh));
+        win[threadIdx.x] = make_uint2((uint32_t)vh | ((uint32_t)vl << 16),
+                                      in_img ? ((uint32_t)sh | ((uint32_t)sl << 16)) : 0u);
+      }
+      __syncthreads();
+      if (ti + (int)gridDim.x < ntiles) fetch(ti + gridDim.x);
+      stage_first_layer(tl, im, win, w1s, sb1, tile, wave, g, n);
+      __syncthreads();
+      if constexpr (KEEP) {
+        // layer 1's output over the tile (without its halo), whole lines
+        for (int t = threadIdx.x; t < kTileH * kTileW * 8; t += 256) {
+          const int px = t >> 3, part = t & 7, py = px / kTileW, pxx = px - py * kTileW;
+          *(u16x8*)(fz.keep + (im.out_off + (int64_t)(tl.y0 + py) * im.Wc + tl.x0 + pxx) * kCh + part * 8) =
+              *(const u16x8*)(tile + ((py + 1) * TW + pxx + 1) * kPxStride + part * 8);
+        }
+      }
+    } else {
 #pragma unroll
-    for (int sidx = 0; sidx < NST; ++sidx) {
-      const int t = threadIdx.x + 256 * sidx;
-      if (t < TH * TW * 8) *(u16x8*)(tile + (t >> 3) * kPxStride + (t & 7) * 8) = pre[sidx];
+      for (int sidx = 0; sidx < NST; ++sidx) {
+        const int t = threadIdx.x + 256 * sidx;
+        if (t < TH * TW * 8) *(u16x8*)(tile + (t >> 3) * kPxStride + (t & 7) * 8) = pre[sidx];
+      }
+      __syncthreads();
+      if (ti + (int)gridDim.x < ntiles) fetch(ti + gridDim.x);
     }
-    __syncthreads();
-    if (ti + (int)gridDim.x < ntiles) fetch(ti + gridDim.x);
     // Two rows at a time: 4 independent accumulators per wave.
 #pragma unroll 1
     for (int r2 = 0; r2 < 4; r2 += 2) {
@@ -243,6 +366,7 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
       for (int r = 0; r < 2; ++r) {
         const int y = tl.y0 + rbase + r2 + r, x = tl.x0 + n;
         const int64_t pix = im.out_off + (int64_t)y * im.Wc + x;  // (the mask's pixel, MODE 1)
+        u16x8 ob;  // kCnnOutTaps: the pixel's 8 outputs of this lane, in the K order of w8a
 #pragma unroll
         for (int cg = 0; cg < 2; ++cg) {
           const int c0 = cbase + 16 * cg + 4 * g;
@@ -260,19 +384,46 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
 #pragma unroll
             for (int q = 0; q < 4; ++q) o[q] = bf2f(m4[q]) > 0.f ? f2bf(acc[r][cg][q]) : (unsigned short)0;
           }
-          uint2 pk;
-          pk.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
-          pk.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
-          *(uint2*)(obuf + ((rbase + r2 + r) * kTileW + n) * kPxStride + c0) = pk;
+          if constexpr (TAPS) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ob[cg * 4 + q] = o[q];
+          }
+          if constexpr (ACT_OUT) {
+            uint2 pk;
+            pk.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
+            pk.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
+            *(uint2*)(obuf + ((rbase + r2 + r) * kTileW + n) * kPxStride + c0) = pk;
+          }
+        }
+        if constexpr (TAPS) {
+          // the wave's 32 channels of pixel (row, n) against the nine taps'
+          // weights: lane (g, n) receives taps 4 g + q of pixel n
+          const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+          const f32x4 tp = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w8a, __builtin_bit_cast(bf16x8, ob), zero, 0, 0, 0);
+          float* part = tpart + (((wave & 1) * kTileH + rbase + r2 + r) * 9) * kTileW;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (4 * g + q < 9) part[(4 * g + q) * kTileW + n] = tp[q];
         }
       }
     }
-    __syncthreads();  // every wave's outputs are in obuf
-    for (int t = threadIdx.x; t < kTileH * kTileW * 8; t += 256) {
-      const int px = t >> 3, part = t & 7;
-      const int y = tl.y0 + px / kTileW, x = tl.x0 + px % kTileW;
-      *(u16x8*)(out + (im.out_off + (int64_t)y * im.Wc + x) * kCh + part * 8) =
-          *(const u16x8*)(obuf + px * kPxStride + part * 8);
+    __syncthreads();  // every wave's outputs are in obuf / tpart
+    if constexpr (TAPS) {
+      for (int t = threadIdx.x; t < 9 * kTileH * kTileW; t += 256) {
+        const int tap = t / (kTileH * kTileW), px = t - tap * (kTileH * kTileW);
+        const int py = px / kTileW, pxx = px - py * kTileW;
+        const int i0 = (py * 9 + tap) * kTileW + pxx;
+        const float sum = tpart[i0] + tpart[i0 + kTileH * 9 * kTileW];
+        fz.taps[tap * fz.plane + im.out_off + (int64_t)(tl.y0 + py) * im.Wc + tl.x0 + pxx] = sum;
+      }
+    }
+    if constexpr (ACT_OUT) {
+      for (int t = threadIdx.x; t < kTileH * kTileW * 8; t += 256) {
+        const int px = t >> 3, part = t & 7;
+        const int y = tl.y0 + px / kTileW, x = tl.x0 + px % kTileW;
+        *(u16x8*)(out + (im.out_off + (int64_t)y * im.Wc + x) * kCh + part * 8) =
+            *(const u16x8*)(obuf + px * kPxStride + part * 8);
+      }
     }
   }
 }

@@ -101,6 +101,29 @@ def test_cnn_zero_last_layer_is_identity():
     assert np.array_equal(got, im.astype(np.float32))
 
 
+def test_cnn_inference_equals_the_training_forward():
+    """Inference (abcs_denoise) and a training step's forward run the same
+    kernels, the training variants only also writing the activations that
+    inference keeps on chip (layer 1's output, computed inside the first
+    middle layer's staging, and layer 7's, whose per-tap partial sums feed
+    the last layer): the outputs are the same bits.  The layer-local oracle
+    test below checks those kept activations and the output against the
+    oracle, so it covers inference's arithmetic too.  Images of several
+    tiles, image borders in every tile position, a sigma above 255."""
+    blob = _blob(15)
+    imgs = [synth.synth_image(120, 48, 64).astype(np.float64), synth.synth_image(121, 16, 32).astype(np.float64)]
+    sig = [25.0, 300.0]
+    st = _train_setup(imgs, sig, imgs, blob)
+    _step(st, 1, 0.0, grad=False)
+    plan = st["plan"]
+    outv = stored(plan, st["ws"], "cnn_train", "output", 1)
+    got = _gpu_forward(imgs, sig, blob)
+    for i, im in enumerate(imgs):
+        d = plan.images[i]
+        ref = outv[d["out_offset"]:d["out_offset"] + im.size].reshape(im.shape).astype(np.float32)
+        assert np.array_equal(got[i], ref), (i, float(np.max(np.abs(got[i] - ref))))
+
+
 def _train_setup(images, sigmas, targets, blob):
     import torch
     import paper_2001_09632_amd as g
