@@ -78,17 +78,16 @@ __device__ __forceinline__ int bm3d_nref(int len) {
 // (row * W' + col) in group order.
 // ---------------------------------------------------------------------------
 template <int N2>
-__global__ __launch_bounds__(256) void k_bm3d_match(const ImgDev* __restrict__ imgs, const RefTile* __restrict__ tiles,
-                                                   int ntiles, const float* __restrict__ src,
-                                                   const float* __restrict__ sigma, float tau,
-                                                   const int32_t* __restrict__ gate, int32_t* __restrict__ groups) {
+__device__ __forceinline__ void bm3d_match_tile(int tix, const ImgDev* __restrict__ imgs,
+                                                const RefTile* __restrict__ tiles, const float* __restrict__ src,
+                                                const float* __restrict__ sigma, float tau,
+                                                const int32_t* __restrict__ gate, int32_t* __restrict__ groups) {
   using namespace bm3d;
   constexpr int kSpan = 2 * kHalfWin + 1;    // 39 candidate offsets per axis
   constexpr int kSeg = kSpan + kN1 - 1;      // 46 pixels per search row
   __shared__ float win[kWin * kWin];
-  if ((int)blockIdx.x >= ntiles) return;
-  const RefTile tl = tiles[blockIdx.x];
-  if (gate && (gate[0] == 0 || gate[1 + tl.img] == 0)) return;
+  const RefTile tl = tiles[tix];
+  if (gate && gate[1 + tl.img] == 0) return;
   const ImgDev im = imgs[tl.img];
   if (!(sigma[tl.img] > 0.f)) return;
   const int H = im.Hc, W = im.Wc;
@@ -169,6 +168,20 @@ __global__ __launch_bounds__(256) void k_bm3d_match(const ImgDev* __restrict__ i
 #pragma unroll
   for (int s = 0; s < N2; ++s)
     if (s < n) g[1 + s] = bi[s];
+}
+
+// Workgroups loop over the tiles (a gated launch uses a capped grid, so that
+// an unused fallback costs little more than the launch).
+template <int N2>
+__global__ __launch_bounds__(256) void k_bm3d_match(const ImgDev* __restrict__ imgs, const RefTile* __restrict__ tiles,
+                                                   int ntiles, const float* __restrict__ src,
+                                                   const float* __restrict__ sigma, float tau,
+                                                   const int32_t* __restrict__ gate, int32_t* __restrict__ groups) {
+  if (gate && gate[0] == 0) return;
+  for (int tix = blockIdx.x; tix < ntiles; tix += gridDim.x) {
+    if (tix != (int)blockIdx.x) __syncthreads();  // the previous tile's LDS reads are done
+    bm3d_match_tile<N2>(tix, imgs, tiles, src, sigma, tau, gate, groups);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -268,21 +281,20 @@ __device__ __forceinline__ long long to_fix(double v) { return (long long)llrint
 // STAGE 2: Wiener shrinkage of groups cut from `noisy` with the spectrum of
 //          the same groups cut from `basic`.
 template <int STAGE>
-__global__ __launch_bounds__(256) void k_bm3d_filter(const ImgDev* __restrict__ imgs, const RefTile* __restrict__ tiles,
-                                                    int ntiles, const float* __restrict__ noisy,
-                                                    const float* __restrict__ basic, const float* __restrict__ sigma,
-                                                    const int32_t* __restrict__ groups,
-                                                    const int32_t* __restrict__ gate,
-                                                    unsigned long long* __restrict__ num,
-                                                    unsigned long long* __restrict__ den) {
+__device__ __forceinline__ void bm3d_filter_tile(int tix, const ImgDev* __restrict__ imgs,
+                                                 const RefTile* __restrict__ tiles, const float* __restrict__ noisy,
+                                                 const float* __restrict__ basic, const float* __restrict__ sigma,
+                                                 const int32_t* __restrict__ groups,
+                                                 const int32_t* __restrict__ gate,
+                                                 unsigned long long* __restrict__ num,
+                                                 unsigned long long* __restrict__ den) {
   using namespace bm3d;
   constexpr int N2 = STAGE == 1 ? kN2Ht : kN2Wie;
   __shared__ unsigned long long acc_num[kFiltWin * kFiltWin];
   __shared__ unsigned long long acc_den[kFiltWin * kFiltWin];
   __shared__ float sh[4][64];
-  if ((int)blockIdx.x >= ntiles) return;
-  const RefTile tl = tiles[blockIdx.x];
-  if (gate && (gate[0] == 0 || gate[1 + tl.img] == 0)) return;
+  const RefTile tl = tiles[tix];
+  if (gate && gate[1 + tl.img] == 0) return;
   const ImgDev im = imgs[tl.img];
   const float sg = sigma[tl.img];
   if (!(sg > 0.f)) return;
@@ -381,6 +393,21 @@ __global__ __launch_bounds__(256) void k_bm3d_filter(const ImgDev* __restrict__ 
   }
 }
 
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_bm3d_filter(const ImgDev* __restrict__ imgs, const RefTile* __restrict__ tiles,
+                                                    int ntiles, const float* __restrict__ noisy,
+                                                    const float* __restrict__ basic, const float* __restrict__ sigma,
+                                                    const int32_t* __restrict__ groups,
+                                                    const int32_t* __restrict__ gate,
+                                                    unsigned long long* __restrict__ num,
+                                                    unsigned long long* __restrict__ den) {
+  if (gate && gate[0] == 0) return;
+  for (int tix = blockIdx.x; tix < ntiles; tix += gridDim.x) {
+    if (tix != (int)blockIdx.x) __syncthreads();  // the previous tile's LDS reads are done
+    bm3d_filter_tile<STAGE>(tix, imgs, tiles, noisy, basic, sigma, groups, gate, num, den);
+  }
+}
+
 // out = num / den for images with sigma > 0, out = in for sigma <= 0, NaN
 // for a NaN sigma (no estimate: the matching and filtering kernels skip such
 // an image).
@@ -392,25 +419,24 @@ __global__ __launch_bounds__(256) void k_bm3d_finish(const ImgDev* __restrict__ 
                                                     int64_t pixels, const int32_t* __restrict__ pix_img,
                                                     const int32_t* __restrict__ gate) {
   if (gate && gate[0] == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= pixels) return;
-  const int im = pix_img[i >> kPixChunkShift];
-  if (gate && gate[1 + im] == 0) return;
-  const float sg = sigma[im];
-  if (sg > 0.f) {
-    out[i] = (float)((double)(long long)num[i] / (double)(long long)den[i]);
-  } else if (sg <= 0.f) {
-    out[i] = in[i];
-  } else {
-    out[i] = sg;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < pixels; i += (int64_t)gridDim.x * 256) {
+    const int im = pix_img[i >> kPixChunkShift];
+    if (gate && gate[1 + im] == 0) continue;
+    const float sg = sigma[im];
+    if (sg > 0.f) {
+      out[i] = (float)((double)(long long)num[i] / (double)(long long)den[i]);
+    } else if (sg <= 0.f) {
+      out[i] = in[i];
+    } else {
+      out[i] = sg;
+    }
   }
 }
 
 __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* __restrict__ p, int64_t n,
                                                  const int32_t* __restrict__ gate) {
   if (gate && gate[0] == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0ull;
 }
 
 }  // namespace abcs
