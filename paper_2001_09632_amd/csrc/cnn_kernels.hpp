@@ -41,6 +41,13 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 // float32 -> bfloat16, round to nearest even (v_cvt_pk_bf16_f32; NaN stays NaN).
 __device__ __forceinline__ unsigned short f2bf(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
+// Two float32 -> two bfloat16 (round to nearest even) in one register, a in
+// the low half: one paired conversion, the same bits as f2bf of each.
+__device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
+  typedef float f32x2v __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2v){a, b}, bf16x2v));
+}
 
 // float32 blob -> bfloat16 copies: mid-layer weights in blob order
 // ([C_out][tap][C_in]) and, when wt is not null, their transposes with flipped
@@ -156,13 +163,9 @@ __device__ __forceinline__ void stage_first_layer(const CnnTile& tl, const ImgDe
       // acc[cg][q]: channel 16 cg + 4 g + q of pixel t
       const int c0 = 16 * cg + 4 * g;
       const float4 bb = *(const float4*)(sb1 + c0);
-      const float bq[4] = {bb.x, bb.y, bb.z, bb.w};
-      uint32_t o[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = (uint32_t)f2bf(fmaxf(acc[cg][q] + bq[q], 0.f));
       uint2 pk;
-      pk.x = (o[0] | (o[1] << 16)) & keep;
-      pk.y = (o[2] | (o[3] << 16)) & keep;
+      pk.x = pack_bf2(fmaxf(acc[cg][0] + bb.x, 0.f), fmaxf(acc[cg][1] + bb.y, 0.f)) & keep;
+      pk.y = pack_bf2(fmaxf(acc[cg][2] + bb.z, 0.f), fmaxf(acc[cg][3] + bb.w, 0.f)) & keep;
       *(uint2*)(tile + t * kPxStride + c0) = pk;
     }
   }
@@ -170,24 +173,27 @@ __device__ __forceinline__ void stage_first_layer(const CnnTile& tl, const ImgDe
 
 // out(p) = v(p) - 255 (b8 + sum over taps of t_tap(p + offset_tap)), the
 // planes t_tap written by the last middle layer (kCnnOutTaps), zero outside
-// the image; one thread per pixel, taps in order.  pix_img: the image of
-// each chunk of 2^kPixChunkShift pixels.
+// the image, taps in order.  Two 8 x 16-pixel tiles per workgroup, one
+// pixel per thread.
 __global__ __launch_bounds__(256) void k_cnn_taps_out(const ImgDev* __restrict__ imgs,
-                                                     const int32_t* __restrict__ pix_img, int64_t pixels,
+                                                     const CnnTile* __restrict__ tiles, int ntiles, int64_t pixels,
                                                      const float* __restrict__ taps, const float* __restrict__ v,
                                                      const float* __restrict__ b8p, float* __restrict__ out) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= pixels) return;
-  const ImgDev im = imgs[pix_img[p >> kPixChunkShift]];  // one entry per 64-pixel chunk
-  const int64_t rel = p - im.out_off;
-  const int y = (int)(rel / im.Wc), x = (int)(rel - (int64_t)y * im.Wc);
+  using namespace cnn;
+  const int ti = 2 * blockIdx.x + (threadIdx.x >> 7);
+  if (ti >= ntiles) return;
+  const CnnTile tl = tiles[ti];
+  const ImgDev im = imgs[tl.img];
+  const int y = tl.y0 + ((threadIdx.x & 127) >> 4), x = tl.x0 + (threadIdx.x & 15);
+  const float* tp = taps + im.out_off;
   float sum = 0.f;
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
     const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
     if ((unsigned)yy < (unsigned)im.Hc && (unsigned)xx < (unsigned)im.Wc)
-      sum += taps[tap * pixels + im.out_off + (int64_t)yy * im.Wc + xx];
+      sum += tp[tap * pixels + (int64_t)yy * im.Wc + xx];
   }
+  const int64_t p = im.out_off + (int64_t)y * im.Wc + x;
   out[p] = v[p] - 255.f * (b8p[0] + sum);
 }
 
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
 #pragma unroll
       for (int kc = 0; kc < 2; ++kc)
         wa[cg][tap][kc] = *(const bf16x8*)(w + ((cbase + 16 * cg + n) * 9 + tap) * kCh + 32 * kc + 8 * g);
-  __shared__ float sbias[kCh];
+  __shared__ __attribute__((aligned(16))) float sbias[kCh];
   if (threadIdx.x < kCh) sbias[threadIdx.x] = MODE == 0 ? bias[threadIdx.x] : 0.f;
 
   // The input tile (with its one-pixel halo, zero outside the image) of the
@@ -370,30 +376,31 @@ __global__ __launch_bounds__(256, 2) void k_cnn_mid(const ImgDev* __restrict__ i
 #pragma unroll
         for (int cg = 0; cg < 2; ++cg) {
           const int c0 = cbase + 16 * cg + 4 * g;
-          unsigned short o[4];
+          uint2 pk;  // the four outputs as bfloat16, channel c0 in the low half of x
           if (MODE == 0) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) o[q] = f2bf(fmaxf(acc[r][cg][q] + sbias[c0 + q], 0.f));
+            const float4 bb = *(const float4*)(sbias + c0);
+            pk.x = pack_bf2(fmaxf(acc[r][cg][0] + bb.x, 0.f), fmaxf(acc[r][cg][1] + bb.y, 0.f));
+            pk.y = pack_bf2(fmaxf(acc[r][cg][2] + bb.z, 0.f), fmaxf(acc[r][cg][3] + bb.w, 0.f));
           } else if (MODE == 2) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) o[q] = f2bf(acc[r][cg][q]);
+            pk.x = pack_bf2(acc[r][cg][0], acc[r][cg][1]);
+            pk.y = pack_bf2(acc[r][cg][2], acc[r][cg][3]);
           } else {
             const uint2 mk = *(const uint2*)(mask + pix * kCh + c0);
             const unsigned short m4[4] = {(unsigned short)(mk.x & 0xffff), (unsigned short)(mk.x >> 16),
                                           (unsigned short)(mk.y & 0xffff), (unsigned short)(mk.y >> 16)};
+            unsigned short o[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) o[q] = bf2f(m4[q]) > 0.f ? f2bf(acc[r][cg][q]) : (unsigned short)0;
-          }
-          if constexpr (TAPS) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) ob[cg * 4 + q] = o[q];
-          }
-          if constexpr (ACT_OUT) {
-            uint2 pk;
             pk.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
             pk.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
-            *(uint2*)(obuf + ((rbase + r2 + r) * kTileW + n) * kPxStride + c0) = pk;
           }
+          if constexpr (TAPS) {
+            ob[cg * 4 + 0] = (unsigned short)(pk.x & 0xffff);
+            ob[cg * 4 + 1] = (unsigned short)(pk.x >> 16);
+            ob[cg * 4 + 2] = (unsigned short)(pk.y & 0xffff);
+            ob[cg * 4 + 3] = (unsigned short)(pk.y >> 16);
+          }
+          if constexpr (ACT_OUT) *(uint2*)(obuf + ((rbase + r2 + r) * kTileW + n) * kPxStride + c0) = pk;
         }
         if constexpr (TAPS) {
           // the wave's 32 channels of pixel (row, n) against the nine taps'
