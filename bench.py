@@ -125,7 +125,7 @@ TRAFFIC = {
 # instruction, FMA = 2 flops; an upper bound, masked lanes count); keyed like
 # TRAFFIC by the sources that define the kernels.
 BM3D_FP32 = dict(sources=("csrc/bm3d_kernels.hpp",),
-                 sha256="c374beb06b2ce67cc8779ca2fd4363525e0c2c02c5ad3490ccd4c12ec01ee376", flop_per_call=5.41e11)
+                 sha256="0432df4b373cc789e3ad2c121ec95c902704d78ff5d959167eab017ca4c7ce96", flop_per_call=5.41e11)
 FP32_PEAK_TFLOPS = 157.3
 
 
