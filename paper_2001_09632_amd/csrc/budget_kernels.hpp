@@ -482,10 +482,37 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
     return;
   }
 
-  for (int b = tid; b < kApBins; b += kThreads) H[b] = 0;
+  // Histogram of the weights.  DD weights lie in [0, m1] and many blocks
+  // share one: they are counted in kApRep replicas per weight (replica =
+  // thread % kApRep, in REM's space, free until the floors), so that equal
+  // weights in a wavefront meet at most 64 / kApRep to an LDS address, and
+  // the replicas are then added into H.  BBV weights spread over up to
+  // 16,320 values and go to H directly.
+  constexpr int kApRep = 16;
+  const bool rep = im.mode == kModeDD && (im.m1 + 1) * kApRep <= kApBins;
+  for (int b = tid; b < kApBins; b += kThreads) {
+    H[b] = 0;
+    REM[b] = 0;
+  }
   __syncthreads();
-  for (int i = tid; i < nB; i += kThreads) atomicAdd(&H[wg[i] & (kApBins - 1)], 1);
+#pragma unroll 8
+  for (int i = tid; i < nB; i += kThreads) {
+    const int w = wg[i] & (kApBins - 1);
+    if (rep && w <= im.m1)
+      atomicAdd(&REM[w * kApRep + (tid & (kApRep - 1))], 1);
+    else
+      atomicAdd(&H[w], 1);
+  }
   __syncthreads();
+  if (rep) {
+    for (int b = tid; b <= im.m1; b += kThreads) {
+      int32_t c = 0;
+#pragma unroll
+      for (int r = 0; r < kApRep; ++r) c += REM[b * kApRep + r];
+      H[b] += c;
+    }
+    __syncthreads();
+  }
 
   const int64_t cap = im.cap;
   int64_t P = im.pool;
@@ -568,58 +595,67 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
     }
   }
 
+  // The floor of each open weight's share, in H (its counts are no longer
+  // needed): a block's share then takes no division.
+  for (int b = tid; b < kApBins; b += kThreads)
+    if (REM[b] >= 0) H[b] = (int32_t)floor_div_exact(P * (uniform ? 1 : (int64_t)b), S);
+  __syncthreads();
+
   // Blocks in index order, coalesced: wavefront v owns the range
   // [v span, v span + span) and walks it 64 blocks at a time, lane l taking
-  // block base + l, so that ranks among equal remainders and the offsets
-  // follow the index order through ballots and in-wave scans.
+  // block base + l.  A block's share is its weight's floor, plus one for a
+  // remainder above tau or for one of the first `need` remainders equal to
+  // tau in index order, or the cap for a capped weight.  The first pass
+  // gives each wavefront its count of remainders equal to tau and its sum of
+  // shares before the tie rule, so that the wavefronts' first tie ranks and
+  // first offsets follow from two scans; the second writes the shares and
+  // the offsets (in-wave scans).
   const int lane = tid & 63, wave = tid >> 6;
   const int span = (((nB + kWaves - 1) / kWaves) + 63) & ~63;
   const int v0 = min(nB, wave * span), v1 = min(nB, v0 + span);
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes under this one
-  int64_t neq = 0;
-  if (R > 0)
-    for (int base = v0; base < v1; base += 64) {
-      const int i = base + lane;
-      const int32_t rm = i < v1 ? REM[wg[i] & (kApBins - 1)] : -1;
-      neq += __popcll(__ballot(rm >= 0 && rm == tau));
-    }
-  // ranks: wavefronts in order (lane 0 of each holds the wave's count)
-  int64_t rank = group_exclusive_scan(lane == 0 ? neq : (int64_t)0, sh64);
-  rank = __shfl(rank, 0, 64);
   const int32_t add = (im.mode == kModeDD) ? im.m1 : 0;
-  int64_t ksum = 0;
+  int64_t s1 = 0, neq = 0;
+#pragma unroll 8
   for (int base = v0; base < v1; base += 64) {
     const int i = base + lane;
     const bool valid = i < v1;
     const int w = valid ? (wg[i] & (kApBins - 1)) : 0;
     const int32_t rm = valid ? REM[w] : -1;
-    const uint64_t eq = __ballot(R > 0 && rm >= 0 && rm == tau);
-    int64_t ki = cap;
-    if (rm >= 0) {
-      ki = floor_div_exact(P * (uniform ? 1 : (int64_t)w), S);
-      if (R > 0) {
-        if (rm > tau) ki += 1;
-        else if (rm == tau && rank + __popcll(eq & below) < need) ki += 1;
-      }
-    }
-    ki += add;
-    if (valid) kg[i] = (int32_t)ki;
-    rank += __popcll(eq);
-    ksum += wave_sum_t<int64_t>(valid ? ki : 0);
+    neq += __popcll(__ballot(R > 0 && rm >= 0 && rm == tau));
+    if (valid) s1 += (rm >= 0 ? (int64_t)H[w] + ((R > 0 && rm > tau) ? 1 : 0) : cap) + add;
   }
-  int64_t obase = group_exclusive_scan(lane == 0 ? ksum : (int64_t)0, sh64);
+  s1 = wave_sum_t<int64_t>(s1);
+  // ranks: wavefronts in order (lane 0 of each holds the wave's count)
+  int64_t rank = group_exclusive_scan(lane == 0 ? neq : (int64_t)0, sh64);
+  rank = __shfl(rank, 0, 64);
+  const int64_t extra = min(max(need - rank, (int64_t)0), neq);  // the wave's ties that take one more
+  int64_t obase = group_exclusive_scan(lane == 0 ? s1 + extra : (int64_t)0, sh64);
   obase = __shfl(obase, 0, 64) + im.meas_off;
+#pragma unroll 4
   for (int base = v0; base < v1; base += 64) {
     const int i = base + lane;
-    const int32_t kv = i < v1 ? kg[i] : 0;
+    const bool valid = i < v1;
+    const int w = valid ? (wg[i] & (kApBins - 1)) : 0;
+    const int32_t rm = valid ? REM[w] : -1;
+    const bool tie = R > 0 && rm >= 0 && rm == tau;
+    const uint64_t eq = __ballot(tie);
+    int32_t kv = 0;
+    if (valid) {
+      int64_t ki = rm >= 0 ? (int64_t)H[w] + ((R > 0 && rm > tau) ? 1 : 0) : cap;
+      if (tie && rank + __popcll(eq & below) < need) ki += 1;
+      kv = (int32_t)(ki + add);
+      kg[i] = kv;
+    }
     int32_t inc = kv;  // inclusive scan over the 64 lanes
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int32_t u = __shfl_up(inc, o, 64);
       if (lane >= o) inc += u;
     }
-    if (i < v1) og[i] = obase + inc - kv;
+    if (valid) og[i] = obase + inc - kv;
     obase += __shfl(inc, 63, 64);
+    rank += __popcll(eq);
   }
 }
 
