@@ -169,66 +169,6 @@ __device__ __forceinline__ void gen_block_range(const ImgDev& im, const int32_t*
   rel = r;
 }
 
-// ---------------------------------------------------------------------------
-// DD n_i for B = 8 / 32 in float64: T[r][v] = sum_j X[r][j] D[v][j] (j
-// ascending), C[u][v] = sum_r D[u][r] T[r][v] (r ascending), every product
-// and sum rounded on its own; n_i = #{z < m1 : |C[zz(z)]| > T}.
-// ---------------------------------------------------------------------------
-template <int B, int XF>
-__global__ __launch_bounds__(kGroupThreads) void k_gen_dd_stats(const ImgDev* __restrict__ imgs,
-                                                               const Tile* __restrict__ tiles, int ntiles,
-                                                               const uint8_t* __restrict__ px,
-                                                               int32_t* __restrict__ stat) {
-#pragma clang fp contract(off)
-  constexpr int P = B + 1;
-  __shared__ double sDd[B * B];
-  __shared__ uint16_t spos[B * B];
-  __shared__ float sX[kWavesPerGroup][B * P];
-  __shared__ double sT[kWavesPerGroup][B * P];
-  if ((int)blockIdx.x >= ntiles) return;
-  for (int t = threadIdx.x; t < B * B; t += kGroupThreads) {
-    sDd[t] = GenTables<B, XF>::Dd()[t];
-    spos[t] = GenTables<B, XF>::pos()[t];
-  }
-  __syncthreads();
-  const Tile tl = tiles[blockIdx.x];
-  const ImgDev im = imgs[tl.img];
-  const int w = wave_in_group(), lane = threadIdx.x & 63;
-  const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, (B - 1) * im.pitch + B * tl.count);
-  float* X = sX[w];
-  double* T = sT[w];
-  const int m1 = im.m1 < B * B ? im.m1 : B * B;
-  const double thr = (double)im.T;
-  for (int bb = w; bb < tl.count; bb += kWavesPerGroup) {
-    gen_load_pixels<B>(rp, im.pitch, bb, X);
-    wave_lds_sync();
-    for (int idx = lane; idx < B * B; idx += 64) {
-      const int r = idx / B, v = idx - r * B;
-      double s = 0.0;
-      for (int j = 0; j < B; ++j) {
-        const double p = (double)X[r * P + j] * sDd[v * B + j];
-        s = s + p;
-      }
-      T[r * P + v] = s;
-    }
-    wave_lds_sync();
-    int cnt = 0;
-    for (int z = lane; z < m1; z += 64) {
-      const int uv = spos[z];
-      const int u = uv / B, v = uv - u * B;
-      double s = 0.0;
-      for (int r = 0; r < B; ++r) {
-        const double p = sDd[u * B + r] * T[r * P + v];
-        s = s + p;
-      }
-      cnt += fabs(s) > thr ? 1 : 0;
-    }
-    cnt = wave_sum_i32(cnt);
-    if (lane == 0) stat[im.blk_off + tl.first + bb] = cnt;
-    wave_lds_sync();
-  }
-}
-
 // The transform half of an IDA iteration (as k_ida_step16): z^t = y - A x^t
 // + alpha z^{t-1} on the measured coefficients, v = x + A* z^t, and the
 // block's sum of (z^t)^2 in float64 (fixed butterfly order) in part[blk].
@@ -1036,6 +976,241 @@ __global__ __launch_bounds__(kGroupThreads) void k_encode8(const ImgDev* __restr
     const uint32_t off = bx < tl.count ? 4u * (uint32_t)(xrow * im.Wc + 8 * bx + xcol) : 0xffffffffu;
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, X), rout, off, 0, kStoreNT);
   }
+}
+
+// ---------------------------------------------------------------------------
+// DD statistics n_i of B = 32 and B = 8 blocks, screened on the float32
+// matrix cores and exact: the forward transform decides |c| > T for every
+// coefficient of zigzag rank below m1 further than the guard from T; the
+// others are recomputed in float64 in the definition's order (T[r] = sum_j
+// X[r][j] D[v][j], j ascending; c = sum_r D[u][r] T[r], r ascending; every
+// product and sum rounded on its own), B lanes per coefficient: lane r forms
+// row r's sum from the block's pixels, the group's first lane adds the rows'
+// products in order.  Screening errors (u = 2^-24; a float32 sum of n terms
+// errs by at most n u times the sum of their magnitudes; |X| <= 255):
+//   B = 32 (|D| <= 0.25, sum_j |D[v][j]| <= sqrt(32) < 5.66): stage 1, 32
+//     products of magnitude sum <= 1443: 32 u 1443 = 2.8e-3, plus the float32
+//     rounding of D (32 * 255 * 0.25 * 2^-24 = 1.2e-4), so |T| <= 1443.1;
+//     stage 2, magnitude sum <= 8165: 32 u 8165 = 1.56e-2, the stage-1 error
+//     times 5.66 (1.64e-2) and D's rounding on T (32 * 0.25 * 2^-24 * 1443 =
+//     6.9e-4): <= 3.3e-2.  Guard 0.1.
+//   B = 8 (|D| <= 0.5, sum_j |D[v][j]| <= sqrt(8) < 2.83; the quadrant
+//     packing's 16-slot chains add exact zeros for the other blocks): stage
+//     1, magnitude sum <= 721.3: 16 u 721.3 = 6.9e-4 plus D's rounding (8 *
+//     255 * 0.5 * 2^-24 = 6.1e-5), so |T| <= 722; stage 2, magnitude sum <=
+//     2043: 16 u 2043 = 1.95e-3, the stage-1 error times 2.83 (2.1e-3) and
+//     D's rounding on T (8 * 0.5 * 2^-24 * 722 = 1.7e-4): <= 4.3e-3.  Guard
+//     0.02.
+// ---------------------------------------------------------------------------
+constexpr float kDDGuard32 = 0.1f, kDDGuard8 = 0.02f;
+
+// Four wavefronts per tile (a quarter of its blocks each: few, long tiles
+// would leave most SIMDs idle), one block at a time (the truncated
+// transform computes only the output tiles that hold a rank below m1).
+constexpr int kDD32Split = 2;
+
+template <int XF>
+__global__ __launch_bounds__(kGroupThreads) void k_dd_stats32(const ImgDev* __restrict__ imgs,
+                                                             const Tile* __restrict__ tiles, int ntiles,
+                                                             const uint8_t* __restrict__ px,
+                                                             int32_t* __restrict__ stat) {
+#pragma clang fp contract(off)
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= (ntiles << kDD32Split)) return;
+  const Tile tl = split_tile(tiles, wave, kDD32Split, 32);
+  if (tl.count == 0) return;
+  const ImgDev im = imgs[tl.img];
+  Lane32T LT;
+  lane32t_init<XF>(LT);
+  const double* Dd = GenTables<32, XF>::Dd();
+  const int lane = threadIdx.x & 63, lg = lane >> 4, ln = lane & 15;
+  int zr[2][2][4];
+  zz32_ranks<true>(zr);
+  const int m1 = im.m1 < 1024 ? im.m1 : 1024;
+  const float t_hi = (float)im.T + kDDGuard32, t_lo = (float)im.T - kDDGuard32;
+  uint64_t inm[2][2][4];  // lanes whose coefficient in register [i][j][r] has rank below m1
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) inm[i][j][r] = __ballot(zr[i][j][r] < m1);
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, 31 * im.pitch + 32 * tl.count);
+  int32_t my_stat = 0;  // lane b keeps block b's count
+  for (int b = 0; b < tl.count; ++b) {
+    float x[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const uint32_t w =
+            __builtin_amdgcn_raw_buffer_load_b32(rp, (16 * i + ln) * im.pitch + 32 * b + 16 * k + 4 * lg, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[i][k][c] = (float)((w >> (8 * c)) & 0xffu);
+      }
+    f32x4 C[2][2];
+    dct32_fwd_t(x, LT, m1, C);
+    int cnt = 0;
+    uint64_t und[2][2][4];
+    uint64_t any = 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float av = fabsf(C[i][j][r]);
+          const uint64_t gt = __ballot(av > t_hi);
+          const uint64_t ge = __ballot(av >= t_lo);
+          cnt += __popcll(gt & inm[i][j][r]);
+          und[i][j][r] = ge & ~gt & inm[i][j][r];
+          any |= und[i][j][r];
+        }
+    if (any != 0) {
+      // float64 recheck, two coefficients per pass (lanes 32 e .. 32 e + 31)
+      const int e = lane >> 5, rr = lane & 31;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            uint64_t um = und[i][j][r];
+            while (um != 0) {
+              const int l0 = __builtin_ctzll(um);
+              um &= um - 1;
+              int l1 = -1;
+              if (um != 0) {
+                l1 = __builtin_ctzll(um);
+                um &= um - 1;
+              }
+              const int le = e == 0 ? l0 : l1;
+              const bool act = le >= 0;
+              const int ls = act ? le : 0;
+              // register [i][j][r] of lane ls holds C(16i + 4r + g, 16j + s(n))
+              const int u = 16 * i + 4 * r + (ls >> 4);
+              const int v = 16 * j + 4 * ((ls & 15) & 3) + ((ls & 15) >> 2);
+              double t = 0.0;
+              if (act) {
+#pragma unroll 1
+                for (int q = 0; q < 8; ++q) {
+                  const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rp, rr * im.pitch + 32 * b + 4 * q, 0, 0);
+#pragma unroll
+                  for (int c = 0; c < 4; ++c) {
+                    const double p = (double)((w >> (8 * c)) & 0xffu) * Dd[v * 32 + 4 * q + c];
+                    t = t + p;
+                  }
+                }
+              }
+              const double pr = Dd[u * 32 + rr] * t;
+              double acc = 0.0;
+#pragma unroll 1
+              for (int k = 0; k < 32; ++k) acc = acc + __shfl(pr, (lane & 32) + k, 64);
+              cnt += __popcll(__ballot(act && rr == 0 && fabs(acc) > (double)im.T));
+            }
+          }
+    }
+    if (lane == b) my_stat = cnt;
+  }
+  if (lane < tl.count) stat[im.blk_off + tl.first + lane] = my_stat;
+}
+
+// One wavefront per tile, four blocks per transform in the quadrant packing
+// of k_sense8.
+template <int XF>
+__global__ __launch_bounds__(kGroupThreads) void k_dd_stats8(const ImgDev* __restrict__ imgs,
+                                                            const Tile* __restrict__ tiles, int ntiles,
+                                                            const uint8_t* __restrict__ px,
+                                                            int32_t* __restrict__ stat) {
+#pragma clang fp contract(off)
+  const int wave = blockIdx.x * kWavesPerGroup + wave_in_group();
+  if (wave >= ntiles) return;
+  const Tile tl = tiles[wave];
+  const ImgDev im = imgs[tl.img];
+  Lane16 L;
+  lane8x4_init<XF>(L);
+  const double* Dd = GenTables<8, XF>::Dd();
+  const int lane = threadIdx.x & 63;
+  // operand side: block quadrant and pixel row / column of this lane
+  const int xq = 2 * (L.n >> 3) + (L.g >> 1), xrow = L.n & 7, xcol = 4 * (L.g & 1);
+  // output side: block quadrant; register r holds coefficient (4 (g % 2) + r, n % 8)
+  const int oq = 2 * (L.g >> 1) + (L.n >> 3);
+  const int m1 = im.m1 < 64 ? im.m1 : 64;
+  const float t_hi = (float)im.T + kDDGuard8, t_lo = (float)im.T - kDDGuard8;
+  uint64_t inm[4], bq[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) inm[r] = __ballot(c_zzrank8[(4 * (L.g & 1) + r) * 8 + (L.n & 7)] < m1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) bq[q] = __ballot(oq == q);
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(px + tl.px_base, 7 * im.pitch + 8 * tl.count);
+  int32_t my_stat = 0;  // lane b keeps block b's count
+  for (int b0 = 0; b0 < tl.count; b0 += 4) {
+    const int bx = b0 + xq;
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(
+        rp, bx < tl.count ? (uint32_t)(xrow * im.pitch + 8 * bx + xcol) : 0xffffffffu, 0, 0);
+    float a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = (float)((w >> (8 * c)) & 0xffu);
+    const f32x4 C = dct16_fwd(a, L);
+    int cnt[4] = {0, 0, 0, 0};
+    uint64_t und[4], any = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float av = fabsf(C[r]);
+      const uint64_t gt = __ballot(av > t_hi) & inm[r];
+      const uint64_t ge = __ballot(av >= t_lo);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cnt[q] += __popcll(gt & bq[q]);
+      und[r] = ge & ~gt & inm[r];
+      any |= und[r];
+    }
+    if (any != 0) {
+      // float64 recheck, eight coefficients per pass (lanes 8 e .. 8 e + 7)
+      const int e = lane >> 3, rr = lane & 7;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        uint64_t um = und[r];
+        while (um != 0) {
+          int le = -1;  // this lane group's coefficient: the e-th set lane of um
+          uint64_t mm = um;
+          for (int k = 0; k < 8 && mm != 0; ++k) {
+            const int l = __builtin_ctzll(mm);
+            mm &= mm - 1;
+            if (k == e) le = l;
+          }
+          um = mm;
+          const bool act = le >= 0;
+          const int ls = act ? le : 0;
+          const int lgs = ls >> 4, lns = ls & 15;
+          const int q = 2 * (lgs >> 1) + (lns >> 3);  // block b0 + q
+          const int u = 4 * (lgs & 1) + r, v = lns & 7;
+          double t = 0.0;
+          if (act) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const uint32_t pw = __builtin_amdgcn_raw_buffer_load_b32(rp, rr * im.pitch + 8 * (b0 + q) + 4 * h, 0, 0);
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                const double p = (double)((pw >> (8 * c)) & 0xffu) * Dd[v * 8 + 4 * h + c];
+                t = t + p;
+              }
+            }
+          }
+          const double pr = Dd[u * 8 + rr] * t;
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) acc = acc + __shfl(pr, (lane & 56) + k, 64);
+          const bool hit = act && rr == 0 && fabs(acc) > (double)im.T;
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) cnt[qq] += __popcll(__ballot(hit && q == qq));
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (lane == b0 + q) my_stat = cnt[q];
+  }
+  if (lane < tl.count) stat[im.blk_off + tl.first + lane] = my_stat;
 }
 
 }  // namespace abcs
