@@ -289,6 +289,21 @@ __device__ T group_exclusive_scan(T v, T* sh) {
   return base + inc - v;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront on the DPP network
+// (vector-ALU latency, no LDS round trips): within each row of 16 lanes by
+// shifts of 1, 2, 4 and 8 (lanes without a source add 0), then the last lane
+// of row 0 is added to row 1 and 3 and of row 1 (now holding rows 0-1) to
+// rows 2 and 3.
+__device__ __forceinline__ int32_t wave_incl_scan_dpp(int32_t x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+  return x;
+}
+
 // floor(pw / S) for 0 <= pw < 2^53 and 0 < S < 2^53: the float64 quotient is
 // within one of the exact one, which the integer checks then settle.
 __device__ __forceinline__ int64_t floor_div_exact(int64_t pw, int64_t S) {
@@ -632,30 +647,38 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
   const int64_t extra = min(max(need - rank, (int64_t)0), neq);  // the wave's ties that take one more
   int64_t obase = group_exclusive_scan(lane == 0 ? s1 + extra : (int64_t)0, sh64);
   obase = __shfl(obase, 0, 64) + im.meas_off;
-#pragma unroll 4
-  for (int base = v0; base < v1; base += 64) {
-    const int i = base + lane;
-    const bool valid = i < v1;
-    const int w = valid ? (wg[i] & (kApBins - 1)) : 0;
-    const int32_t rm = valid ? REM[w] : -1;
-    const bool tie = R > 0 && rm >= 0 && rm == tau;
-    const uint64_t eq = __ballot(tie);
-    int32_t kv = 0;
-    if (valid) {
-      int64_t ki = rm >= 0 ? (int64_t)H[w] + ((R > 0 && rm > tau) ? 1 : 0) : cap;
-      if (tie && rank + __popcll(eq & below) < need) ki += 1;
-      kv = (int32_t)(ki + add);
-      kg[i] = kv;
-    }
-    int32_t inc = kv;  // inclusive scan over the 64 lanes
+  // (the weights of eight 64-block chunks are loaded before any is used, as
+  // buffer loads that need no branch: past the image they read zero)
+  constexpr int kAhead = 8;
+  const __amdgpu_buffer_rsrc_t rw = make_rsrc(wg, 4 * nB);
+  for (int base0 = v0; base0 < v1; base0 += 64 * kAhead) {
+    int32_t wv[kAhead];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int32_t u = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += u;
+    for (int u = 0; u < kAhead; ++u) {
+      const int i = base0 + 64 * u + lane;
+      const int32_t x = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * (uint32_t)i, 0, 0);
+      wv[u] = i < v1 ? (x & (kApBins - 1)) : -1;
     }
-    if (valid) og[i] = obase + inc - kv;
-    obase += __shfl(inc, 63, 64);
-    rank += __popcll(eq);
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      const int i = base0 + 64 * u + lane;
+      const bool valid = wv[u] >= 0;
+      const int w = valid ? wv[u] : 0;
+      const int32_t rm = valid ? REM[w] : -1;
+      const bool tie = R > 0 && rm >= 0 && rm == tau;
+      const uint64_t eq = __ballot(tie);
+      int32_t kv = 0;
+      if (valid) {
+        int64_t ki = rm >= 0 ? (int64_t)H[w] + ((R > 0 && rm > tau) ? 1 : 0) : cap;
+        if (tie && rank + __popcll(eq & below) < need) ki += 1;
+        kv = (int32_t)(ki + add);
+        kg[i] = kv;
+      }
+      const int32_t inc = wave_incl_scan_dpp(kv);
+      if (valid) og[i] = obase + inc - kv;
+      obase += __builtin_amdgcn_readlane(inc, 63);
+      rank += __popcll(eq);
+    }
   }
 }
 
