@@ -470,11 +470,21 @@ __global__ __launch_bounds__(kApThreads) void k_apportion(const ImgDev* __restri
 // which holds S for images of up to kApHistMaxBlocks blocks.
 constexpr int kApBins = 16384;
 constexpr int kApHistMaxBlocks = 131072;
+// Images of more than kApTailMinBlocks blocks leave the passes over their
+// blocks to k_apportion_hist_spans and k_apportion_hist_tail (one workgroup
+// per span of blocks): the histogram kernel writes, into the image's slot,
+// each weight's floor and remainder and the scalars of the tie rule.  Slot
+// layout (int32 units): floors [kApBins], remainders [kApBins], then int64:
+// tau, need, R > 0, cap, the added m1, the span, 2 spare, each span's ties
+// [16] and each span's sum of shares before the tie rule [16].
+constexpr int kApTailMinBlocks = 8192;
+constexpr int kApSlotInts = 2 * kApBins + 2 * (8 + 2 * 16);
 
 __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restrict__ imgs,
                                                         int32_t* __restrict__ stat_all,
                                                         int32_t* __restrict__ k_all,
-                                                        int64_t* __restrict__ off_all) {
+                                                        int64_t* __restrict__ off_all,
+                                                        int32_t* __restrict__ ap_tab) {
   constexpr int kThreads = 1024, kWaves = kThreads / 64, kPerBin = kApBins / kThreads;
   __shared__ int64_t sh64[kWaves];
   __shared__ int32_t hist[256];
@@ -616,6 +626,26 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
     if (REM[b] >= 0) H[b] = (int32_t)floor_div_exact(P * (uniform ? 1 : (int64_t)b), S);
   __syncthreads();
 
+  if (im.ap_slot >= 0) {
+    // the passes over the blocks go to k_apportion_hist_spans / _tail
+    int32_t* tq = ap_tab + (int64_t)im.ap_slot * kApSlotInts;
+    int32_t* tr = tq + kApBins;
+    int64_t* meta = (int64_t*)(tr + kApBins);
+    for (int b = tid; b < kApBins; b += kThreads) {
+      tq[b] = H[b];
+      tr[b] = REM[b];
+    }
+    if (tid == 0) {
+      meta[0] = tau;
+      meta[1] = need;
+      meta[2] = R > 0 ? 1 : 0;
+      meta[3] = cap;
+      meta[4] = (im.mode == kModeDD) ? im.m1 : 0;
+      meta[5] = (((nB + kWaves - 1) / kWaves) + 63) & ~63;  // span
+    }
+    return;
+  }
+
   // Blocks in index order, coalesced: wavefront v owns the range
   // [v span, v span + span) and walks it 64 blocks at a time, lane l taking
   // block base + l.  A block's share is its weight's floor, plus one for a
@@ -672,6 +702,165 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
         int64_t ki = rm >= 0 ? (int64_t)H[w] + ((R > 0 && rm > tau) ? 1 : 0) : cap;
         if (tie && rank + __popcll(eq & below) < need) ki += 1;
         kv = (int32_t)(ki + add);
+        kg[i] = kv;
+      }
+      const int32_t inc = wave_incl_scan_dpp(kv);
+      if (valid) og[i] = obase + inc - kv;
+      obase += __builtin_amdgcn_readlane(inc, 63);
+      rank += __popcll(eq);
+    }
+  }
+}
+
+// The passes of k_apportion_hist over the blocks of an image with a slot,
+// on many workgroups: the blocks are cut into kApHistWaves spans (the spans
+// of k_apportion_hist's wavefronts), workgroup L kApHistWaves + v taking
+// span v of large image L with four wavefronts, a quarter each.  A block's
+// share before the tie rule and whether its remainder ties with tau depend
+// only on its weight (floors and remainders read from the slot).
+constexpr int kApHistWaves = 16;
+
+struct ApSpan {
+  const int32_t* wg;
+  const int32_t* tq;  // floors
+  const int32_t* tr;  // remainders (-1: capped)
+  int64_t* meta;
+  int64_t tau, need, cap;
+  bool rpos;
+  int32_t add;
+  int v0, v1;   // the span
+  int w0, w1;   // this wavefront's part
+};
+
+__device__ __forceinline__ bool ap_span_init(ApSpan& a, const ImgDev& im, const int32_t* stat_all, int32_t* ap_tab) {
+  const int v = blockIdx.x % kApHistWaves;
+  a.wg = stat_all + im.blk_off;
+  a.tq = ap_tab + (int64_t)im.ap_slot * kApSlotInts;
+  a.tr = a.tq + kApBins;
+  a.meta = (int64_t*)(ap_tab + (int64_t)im.ap_slot * kApSlotInts + 2 * kApBins);
+  a.tau = a.meta[0];
+  a.need = a.meta[1];
+  a.rpos = a.meta[2] != 0;
+  a.cap = a.meta[3];
+  a.add = (int32_t)a.meta[4];
+  const int span = (int)a.meta[5];
+  a.v0 = min(im.nB, v * span);
+  a.v1 = min(im.nB, a.v0 + span);
+  const int wave = threadIdx.x >> 6;
+  const int sub = (((span + 3) / 4) + 63) & ~63;
+  a.w0 = min(a.v1, a.v0 + wave * sub);
+  a.w1 = min(a.v1, a.w0 + sub);
+  return a.v0 < a.v1;
+}
+
+// this wavefront's sum of shares before the tie rule and its count of ties
+__device__ __forceinline__ void ap_span_counts(const ApSpan& a, const ImgDev& im, int64_t& s1, int64_t& neq) {
+  const int lane = threadIdx.x & 63;
+  const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.wg, 4 * im.nB);
+  constexpr int kAhead = 4;
+  s1 = 0;
+  neq = 0;
+  for (int base0 = a.w0; base0 < a.w1; base0 += 64 * kAhead) {
+    int32_t wv[kAhead];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      const int i = base0 + 64 * u + lane;
+      const int32_t x = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * (uint32_t)i, 0, 0);
+      wv[u] = i < a.w1 ? (x & (kApBins - 1)) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      const bool valid = wv[u] >= 0;
+      const int w = valid ? wv[u] : 0;
+      const int32_t rm = valid ? a.tr[w] : -1;
+      neq += __popcll(__ballot(a.rpos && rm >= 0 && rm == a.tau));
+      if (valid) s1 += (rm >= 0 ? (int64_t)a.tq[w] + ((a.rpos && rm > a.tau) ? 1 : 0) : a.cap) + a.add;
+    }
+  }
+  s1 = wave_sum_t<int64_t>(s1);
+}
+
+// Span totals: meta[8 + v] = the span's ties, meta[8 + kApHistWaves + v] =
+// its sum of shares before the tie rule.
+__global__ __launch_bounds__(256) void k_apportion_hist_spans(const ImgDev* __restrict__ imgs,
+                                                             const int32_t* __restrict__ large_imgs, int n_large,
+                                                             const int32_t* __restrict__ stat_all,
+                                                             int32_t* __restrict__ ap_tab) {
+  __shared__ int64_t sh[2][4];
+  const int L = blockIdx.x / kApHistWaves, v = blockIdx.x % kApHistWaves;
+  if (L >= n_large) return;
+  const ImgDev im = imgs[large_imgs[L]];
+  ApSpan a;
+  const bool any = ap_span_init(a, im, stat_all, ap_tab);
+  int64_t s1 = 0, neq = 0;
+  if (any) ap_span_counts(a, im, s1, neq);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][wave] = neq;
+    sh[1][wave] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.meta[8 + v] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    a.meta[8 + kApHistWaves + v] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+  }
+}
+
+// The shares and offsets of span v: its first tie rank and first offset from
+// the totals of the spans before it, each wavefront's from the span's (its
+// counts again, then scans), then k_apportion_hist's last pass.
+__global__ __launch_bounds__(256) void k_apportion_hist_tail(const ImgDev* __restrict__ imgs,
+                                                            const int32_t* __restrict__ large_imgs, int n_large,
+                                                            const int32_t* __restrict__ stat_all,
+                                                            int32_t* __restrict__ k_all,
+                                                            int64_t* __restrict__ off_all,
+                                                            int32_t* __restrict__ ap_tab) {
+  __shared__ int64_t sh64[4];
+  const int L = blockIdx.x / kApHistWaves, v = blockIdx.x % kApHistWaves;
+  if (L >= n_large) return;
+  const ImgDev im = imgs[large_imgs[L]];
+  ApSpan a;
+  if (!ap_span_init(a, im, stat_all, ap_tab)) return;
+  int64_t rank0 = 0, obase0 = im.meas_off;
+  for (int u = 0; u < v; ++u) {
+    const int64_t nu = a.meta[8 + u];
+    obase0 += a.meta[8 + kApHistWaves + u] + min(max(a.need - rank0, (int64_t)0), nu);
+    rank0 += nu;
+  }
+  int64_t s1, neq;
+  ap_span_counts(a, im, s1, neq);
+  const int lane = threadIdx.x & 63;
+  int64_t rank = group_exclusive_scan(lane == 0 ? neq : (int64_t)0, sh64);
+  rank = __shfl(rank, 0, 64) + rank0;
+  const int64_t extra = min(max(a.need - rank, (int64_t)0), neq);
+  int64_t obase = group_exclusive_scan(lane == 0 ? s1 + extra : (int64_t)0, sh64);
+  obase = __shfl(obase, 0, 64) + obase0;
+  int32_t* kg = k_all + im.blk_off;
+  int64_t* og = off_all + im.blk_off;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.wg, 4 * im.nB);
+  constexpr int kAhead = 4;
+  for (int base0 = a.w0; base0 < a.w1; base0 += 64 * kAhead) {
+    int32_t wv[kAhead];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      const int i = base0 + 64 * u + lane;
+      const int32_t x = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rw, 4u * (uint32_t)i, 0, 0);
+      wv[u] = i < a.w1 ? (x & (kApBins - 1)) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      const int i = base0 + 64 * u + lane;
+      const bool valid = wv[u] >= 0;
+      const int w = valid ? wv[u] : 0;
+      const int32_t rm = valid ? a.tr[w] : -1;
+      const bool tie = a.rpos && rm >= 0 && rm == a.tau;
+      const uint64_t eq = __ballot(tie);
+      int32_t kv = 0;
+      if (valid) {
+        int64_t ki = rm >= 0 ? (int64_t)a.tq[w] + ((a.rpos && rm > a.tau) ? 1 : 0) : a.cap;
+        if (tie && rank + __popcll(eq & below) < a.need) ki += 1;
+        kv = (int32_t)(ki + a.add);
         kg[i] = kv;
       }
       const int32_t inc = wave_incl_scan_dpp(kv);

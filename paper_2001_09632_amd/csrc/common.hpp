@@ -37,7 +37,8 @@ struct ImgDev {
   int32_t m1;        // DD phase-1 coefficients
   int32_t T;         // DD threshold
   int32_t cap;       // per-block cap of the apportioned part
-  int32_t pad_;
+  int32_t ap_slot;   // histogram apportionment: slot of the image's tables for the
+                     // multi-workgroup last pass (images of more than 8192 blocks), else -1
 };
 
 // Up to kTileBlocks horizontally adjacent blocks of one block row of one

@@ -60,3 +60,19 @@ def test_apportion_uniform_weights_and_ties():
     reqs = [(0, 16, 0.1, "bbv"), (0, 16, 0.45, "bbv"), (0, 16, 0.3, "dd"), (1, 16, 0.2, "bbv"), (1, 16, 0.25, "dd"),
             (1, 16, 0.4, "dd")]
     _check([flat, two], reqs)
+
+
+def test_apportion_histogram_ties_across_spans():
+    """Images of more than 8192 blocks leave their last pass to many
+    workgroups (a span of blocks each): a flat 2048 x 1024 image at B = 8
+    (32,768 blocks, every BBV weight 0, so every remainder ties and the
+    extra shares run across span and wavefront boundaries), a line pattern
+    with few distinct weights, and a large image under ZZ (no
+    apportionment) in the same plan."""
+    flat = np.full((2048, 1024), 131, dtype=np.uint8)
+    lines = np.zeros((1024, 1536), dtype=np.uint8)
+    lines[:, ::40] = 255
+    lines[::56, :] = 180
+    reqs = [(0, 8, 0.1, "bbv"), (0, 8, 0.37, "bbv"), (0, 8, 0.3, "dd"), (1, 8, 0.2, "bbv"), (1, 8, 0.45, "dd"),
+            (1, 16, 0.3, "dd"), (0, 8, 0.25, "zz")]
+    _check([flat, lines], reqs)
