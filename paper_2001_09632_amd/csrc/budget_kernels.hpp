@@ -289,6 +289,12 @@ __device__ T group_exclusive_scan(T v, T* sh) {
   return base + inc - v;
 }
 
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 // Inclusive prefix sum over the 64 lanes of a wavefront on the DPP network
 // (vector-ALU latency, no LDS round trips): within each row of 16 lanes by
 // shifts of 1, 2, 4 and 8 (lanes without a source add 0), then the last lane
@@ -491,6 +497,7 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
   __shared__ int64_t sel_sh[2];
   __shared__ int32_t H[kApBins];    // blocks per weight
   __shared__ int32_t REM[kApBins];  // remainder of an open weight, -1 otherwise
+  __shared__ int32_t wmax_sh;       // largest weight present
   const ImgDev im = imgs[blockIdx.x];
   const int nB = im.nB;
   int32_t* wg = stat_all + im.blk_off;
@@ -519,15 +526,20 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
     H[b] = 0;
     REM[b] = 0;
   }
+  if (tid == 0) wmax_sh = 0;
   __syncthreads();
+  int wmax = 0;
 #pragma unroll 8
   for (int i = tid; i < nB; i += kThreads) {
     const int w = wg[i] & (kApBins - 1);
+    wmax = max(wmax, w);
     if (rep && w <= im.m1)
       atomicAdd(&REM[w * kApRep + (tid & (kApRep - 1))], 1);
     else
       atomicAdd(&H[w], 1);
   }
+  wmax = wave_max_i32(wmax);
+  if ((tid & 63) == 0) atomicMax(&wmax_sh, wmax);
   __syncthreads();
   if (rep) {
     for (int b = tid; b <= im.m1; b += kThreads) {
@@ -539,11 +551,13 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
     __syncthreads();
   }
 
+  // every pass over the bins stops at the largest weight present
+  const int nbins = wmax_sh + 1;
   const int64_t cap = im.cap;
   int64_t P = im.pool;
   int64_t S = 0;
   bool uniform = false;
-  int wcap = kApBins;  // open weights are those below wcap
+  int wcap = nbins;  // open weights are those below wcap
   for (;;) {
     int64_t sw = 0, na = 0;
     for (int b = tid; b < wcap; b += kThreads) {
@@ -576,7 +590,7 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
 
   // floors and remainders per open weight
   int64_t sq = 0;
-  for (int b = tid; b < kApBins; b += kThreads) {
+  for (int b = tid; b < nbins; b += kThreads) {
     int32_t rm = -1;
     if (b < wcap && H[b] > 0) {
       const int64_t pw = P * (uniform ? 1 : (int64_t)b);
@@ -598,7 +612,7 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
 #pragma unroll
       for (int j = 0; j < kPerBin; ++j) {
         const int b = tid + kThreads * j;
-        const int64_t rm = REM[b];
+        const int64_t rm = b < nbins ? REM[b] : -1;
         if (rm >= 0 && ((uint64_t)rm & hi_mask) == ((uint64_t)tau & hi_mask))
           atomicAdd(&hist[((uint64_t)rm >> shift) & 255u], H[b]);
       }
@@ -622,7 +636,7 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
 
   // The floor of each open weight's share, in H (its counts are no longer
   // needed): a block's share then takes no division.
-  for (int b = tid; b < kApBins; b += kThreads)
+  for (int b = tid; b < nbins; b += kThreads)
     if (REM[b] >= 0) H[b] = (int32_t)floor_div_exact(P * (uniform ? 1 : (int64_t)b), S);
   __syncthreads();
 
@@ -631,7 +645,7 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
     int32_t* tq = ap_tab + (int64_t)im.ap_slot * kApSlotInts;
     int32_t* tr = tq + kApBins;
     int64_t* meta = (int64_t*)(tr + kApBins);
-    for (int b = tid; b < kApBins; b += kThreads) {
+    for (int b = tid; b < nbins; b += kThreads) {
       tq[b] = H[b];
       tr[b] = REM[b];
     }
