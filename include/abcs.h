@@ -20,8 +20,12 @@
  *    launch returns ABCS_EHIP.  Nothing throws or aborts across this ABI.
  *  - Thread safety: plans are immutable after creation and may be used from
  *    several host threads; calls that overlap on the device must not share
- *    output buffers.  The launch table (abcs_set_launch_table) is one per
- *    process.
+ *    output buffers.  One exception: a plan whose largest image has more
+ *    than 8192 and at most 131,072 blocks owns device memory that
+ *    abcs_budget and abcs_encode write (the apportionment's per-image tables
+ *    for its images of more than 8192 blocks), so those calls on one such
+ *    plan must not overlap on the device.  The launch table
+ *    (abcs_set_launch_table) is one per process.
  *
  * Geometry (eq 20; Alg 1 and Alg 2 step 1): an H x W image is cropped to
  * H' = B floor(H/B) rows and W' = B floor(W/B) columns and cut into
