@@ -114,9 +114,9 @@ COPY_KIB = 1048576.0
 TRAFFIC = {
     "sense_decode": dict(
         sources=("csrc/common.hpp", "csrc/transform16.hpp", "csrc/sense_kernels.hpp"),
-        sha256="483e6c1db67f08440ef91c064a4a119924d70ce8304cbbf03f00866165ae9e5c",
-        fetch_kib=58659.36, write_kib=840664.77,
-        copy_fetch_kib=524301.16, copy_write_kib=1048576.0),
+        sha256="8512e41aa27704bb57562ee7ecdbff1390b6b28cd6847511bf57bacc0677b3db",
+        fetch_kib=58694.46, write_kib=840648.46,
+        copy_fetch_kib=524301.21, copy_write_kib=1048576.0),
 }
 
 

@@ -477,14 +477,172 @@ __global__ __launch_bounds__(kApThreads) void k_apportion(const ImgDev* __restri
 constexpr int kApBins = 16384;
 constexpr int kApHistMaxBlocks = 131072;
 // Images of more than kApTailMinBlocks blocks leave the passes over their
-// blocks to k_apportion_hist_spans and k_apportion_hist_tail (one workgroup
-// per span of blocks): the histogram kernel writes, into the image's slot,
-// each weight's floor and remainder and the scalars of the tie rule.  Slot
-// layout (int32 units): floors [kApBins], remainders [kApBins], then int64:
-// tau, need, R > 0, cap, the added m1, the span, 2 spare, each span's ties
-// [16] and each span's sum of shares before the tie rule [16].
+// blocks to workgroups of their own, one per span of blocks (kApSpans spans
+// per image):
+// k_apportion_hist_count adds the spans' weight counts into the image's slot
+// (kept zero between calls: the plan zeroes it, the histogram kernel clears
+// it after reading), the histogram kernel writes back each weight's floor
+// and remainder and the scalars of the tie rule, and k_apportion_hist_spans
+// and k_apportion_hist_tail give the shares and offsets.  Slot layout (int32
+// units): floors [kApBins], remainders [kApBins], counts [kApBins], then
+// int64: tau, need, R > 0, cap, the added m1, the span, the largest weight
+// (int32, kept zero between calls as the counts), 1 spare, each span's
+// ties [kApSpans] and each span's sum of shares before the tie rule
+// [kApSpans].
 constexpr int kApTailMinBlocks = 8192;
-constexpr int kApSlotInts = 2 * kApBins + 2 * (8 + 2 * 16);
+constexpr int kApSpans = 64;  // one per lane in k_apportion_hist_tail's scan over spans
+static_assert(kApSpans == 64, "k_apportion_hist_tail scans the spans one per lane");
+constexpr int kApSlotInts = 3 * kApBins + 2 * (8 + 2 * kApSpans);
+constexpr int kApSlotMeta = 3 * kApBins;  // int32 offset of the int64 part
+constexpr int kApSlotWmax = 6;            // its int64 entry of the largest weight
+
+// The radix select of tau and need (8 bits a pass, from the top) over one
+// wavefront's values val[j] >= 0 (negative: not taking part), each counting
+// cnt[j]: tau is the value at which the count of larger values stays below
+// need and with it reaches need, and need becomes the count of values equal
+// to tau that take one more.  Lane l reads bins
+// 255 - 4l .. 252 - 4l of the wavefront's 256-bin histogram in LDS, so lane
+// order is descending bin order and one scan over lanes counts the values
+// above each bin; nothing waits at a barrier.
+template <int N>
+__device__ __forceinline__ void wave_radix_select(const int32_t (&val)[N], const int32_t (&cnt)[N], int32_t* hist,
+                                                  int64_t S, int64_t& tau, int64_t& need) {
+  const int lane = threadIdx.x & 63;
+  const int bits = 64 - __clzll((unsigned long long)(S - 1));
+  for (int shift = ((bits + 7) / 8) * 8 - 8; shift >= 0; shift -= 8) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hist[4 * lane + k] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t hi_mask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int64_t v = val[j];
+      if (v >= 0 && ((uint64_t)v & hi_mask) == ((uint64_t)tau & hi_mask))
+        atomicAdd(&hist[((uint64_t)v >> shift) & 255u], cnt[j]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    int32_t c[4], tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      c[k] = hist[255 - 4 * lane - k];
+      tot += c[k];
+    }
+    int64_t above = wave_incl_scan_dpp(tot) - tot;
+    int sel = -1;
+    int64_t nn = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t ai = above + c[k];
+      if (sel < 0 && ai >= need && ai - c[k] < need) {
+        sel = 255 - 4 * lane - k;
+        nn = need - (ai - c[k]);
+      }
+      above = ai;
+    }
+    const uint64_t m = __ballot(sel >= 0);
+    if (m != 0) {
+      const int src = __ffsll((unsigned long long)m) - 1;
+      tau |= (int64_t)__builtin_amdgcn_readlane(sel, src) << shift;
+      const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)nn, src);
+      const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)nn >> 32), src);
+      need = (int64_t)(((uint64_t)hi << 32) | lo);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// The passes of k_apportion_hist over the weight bins (the cap rule, each
+// open weight's floor and remainder, the radix select of tau and need) on
+// one wavefront, for weights that span at most kApWaveBins bins: lane l
+// holds bins l + 64 j in registers, every sum is a wavefront reduction and
+// nothing waits at a barrier.  The integer steps, and so the results, are
+// those of the workgroup passes: REM[b] for b < nbins, the floor in H[b]
+// where REM[b] >= 0, and out = {R, tau, need} (lane 0 writes it).
+constexpr int kApWaveBins = 1024;
+__device__ __forceinline__ void ap_bins_wave(int32_t* H, int32_t* REM, int32_t* hist, int nbins, int64_t cap,
+                                             int64_t P, int64_t* out) {
+  constexpr int kJ = kApWaveBins / 64;
+  const int lane = threadIdx.x & 63;
+  int32_t h[kJ];
+#pragma unroll
+  for (int j = 0; j < kJ; ++j) {
+    const int b = lane + 64 * j;
+    h[j] = b < nbins ? H[b] : 0;
+  }
+  int64_t S = 0;
+  bool uniform = false;
+  int wcap = nbins;
+  for (;;) {
+    int64_t sw = 0, na = 0;
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+      const int b = lane + 64 * j;
+      if (b < wcap) {
+        sw += (int64_t)h[j] * b;
+        na += h[j];
+      }
+    }
+    S = wave_sum_t<int64_t>(sw);
+    const int64_t A = wave_sum_t<int64_t>(na);
+    if (A == 0) break;
+    uniform = (S == 0);
+    if (uniform) {
+      S = A;
+      if (P >= cap * S) {
+        P -= cap * A;
+        wcap = 0;
+      }
+      break;
+    }
+    if (P <= 0) break;
+    const int64_t wstar = (cap * S + P - 1) / P;
+    if (wstar >= wcap) break;
+    int64_t nc = 0;
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+      const int b = lane + 64 * j;
+      if (b >= wstar && b < wcap) nc += h[j];
+    }
+    nc = wave_sum_t<int64_t>(nc);
+    if (nc == 0) break;
+    wcap = (int)wstar;
+    P -= cap * nc;
+  }
+  int32_t rmv[kJ], qv[kJ];
+  int64_t sq = 0;
+#pragma unroll
+  for (int j = 0; j < kJ; ++j) {
+    const int b = lane + 64 * j;
+    rmv[j] = -1;
+    qv[j] = 0;
+    if (b < wcap && h[j] > 0) {
+      const int64_t pw = P * (uniform ? 1 : (int64_t)b);
+      const int64_t q = floor_div_exact(pw, S);
+      rmv[j] = (int32_t)(pw - q * S);
+      qv[j] = (int32_t)q;
+      sq += h[j] * q;
+    }
+  }
+  const int64_t R = P - wave_sum_t<int64_t>(sq);
+  int64_t tau = 0, need = R;
+  if (R > 0 && S > 1) wave_radix_select<kJ>(rmv, h, hist, S, tau, need);
+#pragma unroll
+  for (int j = 0; j < kJ; ++j) {
+    const int b = lane + 64 * j;
+    if (b < nbins) {
+      REM[b] = rmv[j];
+      if (rmv[j] >= 0) H[b] = qv[j];
+    }
+  }
+  if (lane == 0) {
+    out[0] = R;
+    out[1] = tau;
+    out[2] = need;
+  }
+}
 
 __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restrict__ imgs,
                                                         int32_t* __restrict__ stat_all,
@@ -498,6 +656,7 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
   __shared__ int32_t H[kApBins];    // blocks per weight
   __shared__ int32_t REM[kApBins];  // remainder of an open weight, -1 otherwise
   __shared__ int32_t wmax_sh;       // largest weight present
+  __shared__ int64_t res_sh[3];     // R, tau, need from ap_bins_wave
   const ImgDev im = imgs[blockIdx.x];
   const int nB = im.nB;
   int32_t* wg = stat_all + im.blk_off;
@@ -521,22 +680,37 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
   // the replicas are then added into H.  BBV weights spread over up to
   // 16,320 values and go to H directly.
   constexpr int kApRep = 16;
-  const bool rep = im.mode == kModeDD && (im.m1 + 1) * kApRep <= kApBins;
-  for (int b = tid; b < kApBins; b += kThreads) {
-    H[b] = 0;
-    REM[b] = 0;
-  }
+  const bool slot = im.ap_slot >= 0;
+  const bool rep = !slot && im.mode == kModeDD && (im.m1 + 1) * kApRep <= kApBins;
   if (tid == 0) wmax_sh = 0;
-  __syncthreads();
   int wmax = 0;
+  if (slot) {
+    // the counts and the largest weight k_apportion_hist_count left in the
+    // slot, which is cleared for the next call
+    int32_t* hc = ap_tab + (int64_t)im.ap_slot * kApSlotInts + 2 * kApBins;
+    int32_t* top = (int32_t*)(ap_tab + (int64_t)im.ap_slot * kApSlotInts + kApSlotMeta) + 2 * kApSlotWmax;
+    wmax = *top;
+    for (int b = tid; b <= wmax; b += kThreads) {
+      H[b] = hc[b];
+      hc[b] = 0;
+    }
+    __syncthreads();
+    if (tid == 0) *top = 0;
+  } else {
+    for (int b = tid; b < kApBins; b += kThreads) {
+      H[b] = 0;
+      REM[b] = 0;
+    }
+    __syncthreads();
 #pragma unroll 8
-  for (int i = tid; i < nB; i += kThreads) {
-    const int w = wg[i] & (kApBins - 1);
-    wmax = max(wmax, w);
-    if (rep && w <= im.m1)
-      atomicAdd(&REM[w * kApRep + (tid & (kApRep - 1))], 1);
-    else
-      atomicAdd(&H[w], 1);
+    for (int i = tid; i < nB; i += kThreads) {
+      const int w = wg[i] & (kApBins - 1);
+      wmax = max(wmax, w);
+      if (rep && w <= im.m1)
+        atomicAdd(&REM[w * kApRep + (tid & (kApRep - 1))], 1);
+      else
+        atomicAdd(&H[w], 1);
+    }
   }
   wmax = wave_max_i32(wmax);
   if ((tid & 63) == 0) atomicMax(&wmax_sh, wmax);
@@ -554,6 +728,14 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
   // every pass over the bins stops at the largest weight present
   const int nbins = wmax_sh + 1;
   const int64_t cap = im.cap;
+  int64_t R, tau, need;
+  if (nbins <= kApWaveBins) {
+    if (tid < 64) ap_bins_wave(H, REM, hist, nbins, cap, im.pool, res_sh);
+    __syncthreads();
+    R = res_sh[0];
+    tau = res_sh[1];
+    need = res_sh[2];
+  } else {
   int64_t P = im.pool;
   int64_t S = 0;
   bool uniform = false;
@@ -600,9 +782,10 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
     }
     REM[b] = rm;
   }
-  const int64_t R = P - group_sum<kWaves>(sq, sh64);
+  R = P - group_sum<kWaves>(sq, sh64);
 
-  int64_t tau = 0, need = R;
+  tau = 0;
+  need = R;
   if (R > 0 && S > 1) {
     const int bits = 64 - __clzll((unsigned long long)(S - 1));
     for (int shift = ((bits + 7) / 8) * 8 - 8; shift >= 0; shift -= 8) {
@@ -639,12 +822,13 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
   for (int b = tid; b < nbins; b += kThreads)
     if (REM[b] >= 0) H[b] = (int32_t)floor_div_exact(P * (uniform ? 1 : (int64_t)b), S);
   __syncthreads();
+  }
 
   if (im.ap_slot >= 0) {
     // the passes over the blocks go to k_apportion_hist_spans / _tail
     int32_t* tq = ap_tab + (int64_t)im.ap_slot * kApSlotInts;
     int32_t* tr = tq + kApBins;
-    int64_t* meta = (int64_t*)(tr + kApBins);
+    int64_t* meta = (int64_t*)(tq + kApSlotMeta);
     for (int b = tid; b < nbins; b += kThreads) {
       tq[b] = H[b];
       tr[b] = REM[b];
@@ -655,7 +839,7 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
       meta[2] = R > 0 ? 1 : 0;
       meta[3] = cap;
       meta[4] = (im.mode == kModeDD) ? im.m1 : 0;
-      meta[5] = (((nB + kWaves - 1) / kWaves) + 63) & ~63;  // span
+      meta[5] = (((nB + kApSpans - 1) / kApSpans) + 63) & ~63;  // span
     }
     return;
   }
@@ -727,12 +911,11 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
 }
 
 // The passes of k_apportion_hist over the blocks of an image with a slot,
-// on many workgroups: the blocks are cut into kApHistWaves spans (the spans
-// of k_apportion_hist's wavefronts), workgroup L kApHistWaves + v taking
-// span v of large image L with four wavefronts, a quarter each.  A block's
-// share before the tie rule and whether its remainder ties with tau depend
-// only on its weight (floors and remainders read from the slot).
-constexpr int kApHistWaves = 16;
+// on many workgroups: the blocks are cut into kApSpans spans, workgroup
+// L kApSpans + v taking span v of large image L with four wavefronts, a
+// quarter each.  A block's share before the tie rule and whether its
+// remainder ties with tau depend only on its weight (floors and remainders
+// read from the slot).
 
 struct ApSpan {
   const int32_t* wg;
@@ -747,11 +930,11 @@ struct ApSpan {
 };
 
 __device__ __forceinline__ bool ap_span_init(ApSpan& a, const ImgDev& im, const int32_t* stat_all, int32_t* ap_tab) {
-  const int v = blockIdx.x % kApHistWaves;
+  const int v = blockIdx.x % kApSpans;
   a.wg = stat_all + im.blk_off;
   a.tq = ap_tab + (int64_t)im.ap_slot * kApSlotInts;
   a.tr = a.tq + kApBins;
-  a.meta = (int64_t*)(ap_tab + (int64_t)im.ap_slot * kApSlotInts + 2 * kApBins);
+  a.meta = (int64_t*)(ap_tab + (int64_t)im.ap_slot * kApSlotInts + kApSlotMeta);
   a.tau = a.meta[0];
   a.need = a.meta[1];
   a.rpos = a.meta[2] != 0;
@@ -794,14 +977,70 @@ __device__ __forceinline__ void ap_span_counts(const ApSpan& a, const ImgDev& im
   s1 = wave_sum_t<int64_t>(s1);
 }
 
-// Span totals: meta[8 + v] = the span's ties, meta[8 + kApHistWaves + v] =
-// its sum of shares before the tie rule.
+// The weight counts of span v of large image L, added into the image's slot.  They are
+// counted in LDS first, DD weights (at most m1) in kApRep replicas per weight
+// as in k_apportion_hist, BBV weights one bin per value; the workgroup then
+// adds each weight present into the slot with one global atomic.
+__global__ __launch_bounds__(256) void k_apportion_hist_count(const ImgDev* __restrict__ imgs,
+                                                             const int32_t* __restrict__ large_imgs, int n_large,
+                                                             const int32_t* __restrict__ stat_all,
+                                                             int32_t* __restrict__ ap_tab) {
+  constexpr int kApRep = 16, kMaxW = kApBins / kApRep;  // DD weights kept in replicas: below kMaxW
+  __shared__ __align__(16) int32_t cnt[kApBins];
+  __shared__ int32_t wmax_sh;
+  const int L = blockIdx.x / kApSpans, v = blockIdx.x % kApSpans;
+  if (L >= n_large) return;
+  const ImgDev im = imgs[large_imgs[L]];
+  const int nB = im.nB;
+  const int span = (((nB + kApSpans - 1) / kApSpans) + 63) & ~63;
+  const int v0 = min(nB, v * span), v1 = min(nB, v0 + span);
+  if (v0 >= v1) return;
+  const int32_t* wg = stat_all + im.blk_off;
+  int32_t* hc = ap_tab + (int64_t)im.ap_slot * kApSlotInts + 2 * kApBins;
+  const int tid = threadIdx.x;
+  const bool rep = im.mode == kModeDD && im.m1 < kMaxW;
+  const int nzero = rep ? (im.m1 + 1) * kApRep : kApBins;
+  for (int b = 4 * tid; b < nzero; b += 4 * 256) *(int4*)&cnt[b] = make_int4(0, 0, 0, 0);
+  if (tid == 0) wmax_sh = 0;
+  __syncthreads();
+  int wmax = 0;
+#pragma unroll 8
+  for (int i = v0 + tid; i < v1; i += 256) {
+    const int w = wg[i] & (kApBins - 1);
+    wmax = max(wmax, w);
+    if (!rep)
+      atomicAdd(&cnt[w], 1);
+    else if (w <= im.m1)
+      atomicAdd(&cnt[w * kApRep + (tid & (kApRep - 1))], 1);
+    else
+      atomicAdd(&hc[w], 1);  // outside DD's range: not expected
+  }
+  wmax = wave_max_i32(wmax);
+  if ((tid & 63) == 0) atomicMax(&wmax_sh, wmax);
+  __syncthreads();
+  if (tid == 0)
+    atomicMax((int32_t*)(ap_tab + (int64_t)im.ap_slot * kApSlotInts + kApSlotMeta) + 2 * kApSlotWmax, wmax_sh);
+  const int wtop = rep ? min(wmax_sh, im.m1) : wmax_sh;
+  for (int w = tid; w <= wtop; w += 256) {
+    int32_t c = 0;
+    if (rep) {
+#pragma unroll
+      for (int r = 0; r < kApRep; ++r) c += cnt[w * kApRep + r];
+    } else {
+      c = cnt[w];
+    }
+    if (c > 0) atomicAdd(&hc[w], c);
+  }
+}
+
+// Span totals: meta[8 + v] = the span's ties, meta[8 + kApSpans + v] = its
+// sum of shares before the tie rule.
 __global__ __launch_bounds__(256) void k_apportion_hist_spans(const ImgDev* __restrict__ imgs,
                                                              const int32_t* __restrict__ large_imgs, int n_large,
                                                              const int32_t* __restrict__ stat_all,
                                                              int32_t* __restrict__ ap_tab) {
   __shared__ int64_t sh[2][4];
-  const int L = blockIdx.x / kApHistWaves, v = blockIdx.x % kApHistWaves;
+  const int L = blockIdx.x / kApSpans, v = blockIdx.x % kApSpans;
   if (L >= n_large) return;
   const ImgDev im = imgs[large_imgs[L]];
   ApSpan a;
@@ -816,7 +1055,7 @@ __global__ __launch_bounds__(256) void k_apportion_hist_spans(const ImgDev* __re
   __syncthreads();
   if (threadIdx.x == 0) {
     a.meta[8 + v] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-    a.meta[8 + kApHistWaves + v] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    a.meta[8 + kApSpans + v] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
   }
 }
 
@@ -830,20 +1069,22 @@ __global__ __launch_bounds__(256) void k_apportion_hist_tail(const ImgDev* __res
                                                             int64_t* __restrict__ off_all,
                                                             int32_t* __restrict__ ap_tab) {
   __shared__ int64_t sh64[4];
-  const int L = blockIdx.x / kApHistWaves, v = blockIdx.x % kApHistWaves;
+  const int L = blockIdx.x / kApSpans, v = blockIdx.x % kApSpans;
   if (L >= n_large) return;
   const ImgDev im = imgs[large_imgs[L]];
   ApSpan a;
   if (!ap_span_init(a, im, stat_all, ap_tab)) return;
-  int64_t rank0 = 0, obase0 = im.meas_off;
-  for (int u = 0; u < v; ++u) {
-    const int64_t nu = a.meta[8 + u];
-    obase0 += a.meta[8 + kApHistWaves + u] + min(max(a.need - rank0, (int64_t)0), nu);
-    rank0 += nu;
-  }
+  // the spans before this one, lane u taking span u: ties before each span
+  // (a scan of the counts, each below 2^31), its extra shares, the totals
+  const int lane = threadIdx.x & 63;
+  const int32_t nu = lane < v ? (int32_t)a.meta[8 + lane] : 0;
+  const int64_t su = lane < v ? a.meta[8 + kApSpans + lane] : 0;
+  const int32_t nu_incl = wave_incl_scan_dpp(nu);
+  const int64_t xu = min(max(a.need - (int64_t)(nu_incl - nu), (int64_t)0), (int64_t)nu);
+  const int64_t rank0 = __builtin_amdgcn_readlane(nu_incl, 63);
+  const int64_t obase0 = im.meas_off + wave_sum_t<int64_t>(su + xu);
   int64_t s1, neq;
   ap_span_counts(a, im, s1, neq);
-  const int lane = threadIdx.x & 63;
   int64_t rank = group_exclusive_scan(lane == 0 ? neq : (int64_t)0, sh64);
   rank = __shfl(rank, 0, 64) + rank0;
   const int64_t extra = min(max(a.need - rank, (int64_t)0), neq);
@@ -903,6 +1144,7 @@ __device__ __forceinline__ void apportion_image_reg(const ImgDev& im, int32_t* _
                                                     int32_t* __restrict__ k_all, int64_t* __restrict__ off_all,
                                                     ApportionLds<kThreads>& al) {
   constexpr int kWaves = kThreads / 64;
+  static_assert(kThreads >= 256, "the radix select reads 256 bins, one per thread");
   int64_t* sh64 = al.sh64;
   int32_t* hist = al.hist;
   int64_t* sel_sh = al.sel_sh;

@@ -14,9 +14,16 @@ from gpu_util import Run, pack_images
 pytestmark = pytest.mark.gpu
 
 
-def _check(imgs, reqs):
+def _check(imgs, reqs, calls=1):
+    """calls > 1: the budget runs that many times on one plan (outputs
+    refilled between calls), and the last call's outputs are checked."""
     px, d = pack_images(imgs)
-    run = Run(px, [dict(d[s], block=B, subrate=cr, method=m) for s, B, cr, m in reqs]).budget().fetch()
+    run = Run(px, [dict(d[s], block=B, subrate=cr, method=m) for s, B, cr, m in reqs]).budget()
+    for _ in range(calls - 1):
+        for t in (run.k, run.off, run.stat):
+            t.fill_(-7)
+        run.budget()
+    run.fetch()
     for j, (s, B, cr, m) in enumerate(reqs):
         got = run.image(j)
         k, stat = orc.budget(imgs[s], B, cr, orc.METHOD_NAMES[m])
@@ -40,7 +47,7 @@ def test_apportion_kernels_by_image_size(size, B):
 def test_apportion_histogram_kernel_many_weights():
     """73,728 blocks (2048 x 2304 at B = 8), BBV weights spread widely."""
     big = synth.synth_image(4002, 2048, 2304)
-    _check([big], [(0, 8, 0.2, "bbv"), (0, 8, 0.45, "dd")])
+    _check([big], [(0, 8, 0.2, "bbv"), (0, 8, 0.45, "dd")], calls=2)
 
 
 def test_apportion_global_memory_kernel():
@@ -68,11 +75,30 @@ def test_apportion_histogram_ties_across_spans():
     (32,768 blocks, every BBV weight 0, so every remainder ties and the
     extra shares run across span and wavefront boundaries), a line pattern
     with few distinct weights, and a large image under ZZ (no
-    apportionment) in the same plan."""
+    apportionment) in the same plan.  Three calls on one plan: the weight
+    counts these images leave in the plan's tables must not carry over."""
     flat = np.full((2048, 1024), 131, dtype=np.uint8)
     lines = np.zeros((1024, 1536), dtype=np.uint8)
     lines[:, ::40] = 255
     lines[::56, :] = 180
     reqs = [(0, 8, 0.1, "bbv"), (0, 8, 0.37, "bbv"), (0, 8, 0.3, "dd"), (1, 8, 0.2, "bbv"), (1, 8, 0.45, "dd"),
             (1, 16, 0.3, "dd"), (0, 8, 0.25, "zz")]
-    _check([flat, lines], reqs)
+    _check([flat, lines], reqs, calls=3)
+
+
+def test_apportion_histogram_weights_beyond_one_wavefront():
+    """BBV weights of uniform noise span more than 1024 values, so the passes
+    over the weight bins take the workgroup form rather than the
+    one-wavefront form: a 2048 x 1024 image at B = 8 (32,768 blocks, passes
+    over the blocks on many workgroups) and a 1024 x 512 one (8192 blocks,
+    all passes in the histogram kernel) in one plan, at two rates, beside DD
+    (few weights: the one-wavefront form)."""
+    rng = np.random.default_rng(4004)
+    big = rng.integers(0, 256, size=(2048, 1024), dtype=np.uint8)
+    mid = rng.integers(0, 256, size=(1024, 512), dtype=np.uint8)
+    for img in (big, mid):
+        _, stat = orc.budget(img, 8, 0.3, orc.METHOD_NAMES["bbv"])
+        assert stat.max() >= 1024, "the weights must span more than one wavefront's bins"
+    reqs = [(0, 8, 0.2, "bbv"), (1, 8, 0.2, "bbv"), (0, 8, 0.45, "bbv"), (1, 8, 0.45, "bbv"), (0, 8, 0.3, "dd"),
+            (1, 8, 0.3, "dd")]
+    _check([big, mid], reqs, calls=2)
