@@ -1135,9 +1135,97 @@ __global__ __launch_bounds__(256) void k_apportion_hist_tail(const ImgDev* __res
 template <int kThreads>
 struct ApportionLds {
   int64_t sh64[kThreads / 64];
+  int64_t sh64b[kThreads / 64];
   int32_t hist[256];
   int64_t sel_sh[2];
 };
+
+// Sums (or exclusive prefix sums in thread order) of two values over the
+// workgroup, with one pair of barriers for both.
+template <int NW>
+__device__ __forceinline__ void group_sum2(int64_t& a, int64_t& b, int64_t* sa, int64_t* sb) {
+  a = wave_sum_t(a);
+  b = wave_sum_t(b);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sa[w] = a;
+    sb[w] = b;
+  }
+  __syncthreads();
+  a = 0;
+  b = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    a += sa[i];
+    b += sb[i];
+  }
+}
+
+template <int NW>
+__device__ __forceinline__ void group_exclusive_scan2(int64_t& a, int64_t& b, int64_t* sa, int64_t* sb) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t ia = a, ib = b;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t ua = __shfl_up(ia, o, 64), ub = __shfl_up(ib, o, 64);
+    if (lane >= o) {
+      ia += ua;
+      ib += ub;
+    }
+  }
+  __syncthreads();
+  if (lane == 63) {
+    sa[w] = ia;
+    sb[w] = ib;
+  }
+  __syncthreads();
+  int64_t ba = 0, bb = 0;
+  for (int i = 0; i < w; ++i) {
+    ba += sa[i];
+    bb += sb[i];
+  }
+  a = ba + ia - a;
+  b = bb + ib - b;
+}
+
+// One pass of the workgroup radix select after its histogram is complete:
+// the first wavefront reads the 256 bins (lane l: bins 255 - 4l .. 252 - 4l,
+// so lane order is descending bin order and one DPP scan over lanes counts
+// the values above each bin), clears them for the next pass, and writes the
+// selected digit and the count still needed to sel_sh.
+__device__ __forceinline__ void radix_select_digit_wave(int32_t* hist, int64_t need, int64_t* sel_sh) {
+  const int lane = threadIdx.x & 63;
+  int32_t c[4], tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    c[k] = hist[255 - 4 * lane - k];
+    hist[255 - 4 * lane - k] = 0;
+    tot += c[k];
+  }
+  int64_t above = wave_incl_scan_dpp(tot) - tot;
+  int sel = -1;
+  int64_t nn = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t ai = above + c[k];
+    if (sel < 0 && ai >= need && ai - c[k] < need) {
+      sel = 255 - 4 * lane - k;
+      nn = need - (ai - c[k]);
+    }
+    above = ai;
+  }
+  const uint64_t m = __ballot(sel >= 0);
+  if (m == 0) {
+    if (lane == 0) {
+      sel_sh[0] = 0;
+      sel_sh[1] = need;
+    }
+  } else if (lane == __ffsll((unsigned long long)m) - 1) {
+    sel_sh[0] = sel;
+    sel_sh[1] = nn;
+  }
+}
 
 template <int kThreads, int kPer>
 __device__ __forceinline__ void apportion_image_reg(const ImgDev& im, int32_t* __restrict__ stat_all,
@@ -1154,6 +1242,7 @@ __device__ __forceinline__ void apportion_image_reg(const ImgDev& im, int32_t* _
   int64_t* og = off_all + im.blk_off;
   const int tid = threadIdx.x;
   const int i0 = tid * kPer;
+  const int wave = tid >> 6;
 
   if (im.mode == kModeZZ) {
     for (int i = tid; i < nB; i += kThreads) {
@@ -1175,10 +1264,17 @@ __device__ __forceinline__ void apportion_image_reg(const ImgDev& im, int32_t* _
     kv[j] = valid ? -1 : 0;
     rem[j] = -1;
   }
+  // the radix select's bins start at zero (each of its passes leaves them
+  // so); barriers follow before its first pass
+  if (tid < 256) hist[tid] = 0;
   const int64_t cap = im.cap;
   int64_t P = im.pool;
   int64_t S = 0;
   bool uniform = false;
+  // A round's capped blocks are the drop in the open count seen by the next
+  // round's sums, so the pool shrinks there (cap per block) and a round that
+  // caps nothing ends the loop with the same S.
+  int64_t A_prev = -1;
   for (;;) {
     int64_t sw = 0, na = 0;
 #pragma unroll
@@ -1187,25 +1283,28 @@ __device__ __forceinline__ void apportion_image_reg(const ImgDev& im, int32_t* _
         sw += wv[j];
         na += 1;
       }
-    S = group_sum<kWaves>(sw, sh64);
-    const int64_t A = group_sum<kWaves>(na, sh64);
+    group_sum2<kWaves>(sw, na, sh64, al.sh64b);
+    S = sw;
+    const int64_t A = na;
+    if (A_prev >= 0) {
+      if (A == A_prev) {
+        uniform = (S == 0);
+        if (uniform) S = A;
+        break;
+      }
+      P -= cap * (A_prev - A);
+    }
     if (A == 0) break;
     uniform = (S == 0);
     if (uniform) S = A;
     const int64_t capS = cap * S;
-    int64_t used = 0;
 #pragma unroll
     for (int j = 0; j < kPer; ++j)
       if (kv[j] < 0) {
         const int64_t wi = uniform ? 1 : (int64_t)wv[j];
-        if (P * wi >= capS) {
-          kv[j] = (int32_t)cap;
-          used += cap;
-        }
+        if (P * wi >= capS) kv[j] = (int32_t)cap;
       }
-    used = group_sum<kWaves>(used, sh64);
-    if (used == 0) break;
-    P -= used;
+    A_prev = A;
   }
 
   int64_t sq = 0;
@@ -1225,39 +1324,33 @@ __device__ __forceinline__ void apportion_image_reg(const ImgDev& im, int32_t* _
   if (R > 0 && S > 1) {
     const int bits = 64 - __clzll((unsigned long long)(S - 1));
     for (int shift = ((bits + 7) / 8) * 8 - 8; shift >= 0; shift -= 8) {
-      if (tid < 256) hist[tid] = 0;
-      __syncthreads();
       const uint64_t hi_mask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
 #pragma unroll
       for (int j = 0; j < kPer; ++j)
         if (rem[j] >= 0 && ((uint64_t)rem[j] & hi_mask) == ((uint64_t)tau & hi_mask))
           atomicAdd(&hist[((uint64_t)rem[j] >> shift) & 255u], 1);
       __syncthreads();
-      if (tid == 0) {
-        sel_sh[0] = 0;
-        sel_sh[1] = need;
-      }
-      const int32_t bin = tid < 256 ? hist[255 - tid] : 0;
-      const int64_t above_incl = group_exclusive_scan((int64_t)bin, sh64) + bin;
-      if (tid < 256 && above_incl >= need && above_incl - bin < need) {
-        sel_sh[0] = 255 - tid;
-        sel_sh[1] = need - (above_incl - bin);
-      }
+      if (wave == 0) radix_select_digit_wave(hist, need, sel_sh);
       __syncthreads();
       tau |= (int64_t)sel_sh[0] << shift;
       need = sel_sh[1];
-      __syncthreads();
     }
   }
 
-  int64_t neq = 0;
-  if (R > 0) {
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) neq += (rem[j] == tau) ? 1 : 0;
-  }
-  int64_t rank = group_exclusive_scan(neq, sh64);
+  // Ties with tau take one more in index order while `need` lasts.  One
+  // paired scan gives each thread its first tie rank and the sum of the
+  // shares before it without the tie rule; the ties before it that took one
+  // more are min(need, rank) of them.
+  int64_t neq = 0, ksum = 0;
   const int32_t add = (im.mode == kModeDD) ? im.m1 : 0;
-  int64_t ksum = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    if (R > 0 && rem[j] == tau) neq += 1;
+    if (i0 + j < nB) ksum += (int64_t)kv[j] + ((R > 0 && rem[j] >= 0 && rem[j] > tau) ? 1 : 0) + add;
+  }
+  int64_t rank = neq, kexcl = ksum;
+  group_exclusive_scan2<kWaves>(rank, kexcl, sh64, al.sh64b);
+  int64_t base = kexcl + min(need, rank) + im.meas_off;
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
     int64_t ki = kv[j];
@@ -1271,9 +1364,7 @@ __device__ __forceinline__ void apportion_image_reg(const ImgDev& im, int32_t* _
     }
     ki += add;
     kv[j] = (int32_t)ki;
-    if (i0 + j < nB) ksum += ki;
   }
-  int64_t base = group_exclusive_scan(ksum, sh64) + im.meas_off;
 #pragma unroll
   for (int j = 0; j < kPer; ++j)
     if (i0 + j < nB) {
