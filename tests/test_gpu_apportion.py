@@ -102,3 +102,14 @@ def test_apportion_histogram_weights_beyond_one_wavefront():
     reqs = [(0, 8, 0.2, "bbv"), (1, 8, 0.2, "bbv"), (0, 8, 0.45, "bbv"), (1, 8, 0.45, "bbv"), (0, 8, 0.3, "dd"),
             (1, 8, 0.3, "dd")]
     _check([big, mid], reqs, calls=2)
+
+
+def test_apportion_spans_empty_and_ragged():
+    """Images just past the 8192-block threshold leave most of their 64
+    spans empty: 800 x 656 at B = 8 (8200 blocks, spans of 192, the last 21
+    empty) and 1000 x 1032 (16,125 blocks, a ragged last span), BBV and DD,
+    two calls on one plan."""
+    a = synth.synth_image(4005, 800, 656)
+    b = synth.synth_image(4006, 1000, 1032)
+    reqs = [(0, 8, 0.25, "bbv"), (0, 8, 0.4, "dd"), (1, 8, 0.15, "bbv"), (1, 8, 0.35, "dd")]
+    _check([a, b], reqs, calls=2)
