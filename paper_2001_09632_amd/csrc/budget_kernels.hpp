@@ -496,6 +496,93 @@ constexpr int kApSlotInts = 3 * kApBins + 2 * (8 + 2 * kApSpans);
 constexpr int kApSlotMeta = 3 * kApBins;  // int32 offset of the int64 part
 constexpr int kApSlotWmax = 6;            // its int64 entry of the largest weight
 
+// Sums (or exclusive prefix sums in thread order) of two values over the
+// workgroup, with one pair of barriers for both.
+template <int NW>
+__device__ __forceinline__ void group_sum2(int64_t& a, int64_t& b, int64_t* sa, int64_t* sb) {
+  a = wave_sum_t(a);
+  b = wave_sum_t(b);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sa[w] = a;
+    sb[w] = b;
+  }
+  __syncthreads();
+  a = 0;
+  b = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    a += sa[i];
+    b += sb[i];
+  }
+}
+
+template <int NW>
+__device__ __forceinline__ void group_exclusive_scan2(int64_t& a, int64_t& b, int64_t* sa, int64_t* sb) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t ia = a, ib = b;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t ua = __shfl_up(ia, o, 64), ub = __shfl_up(ib, o, 64);
+    if (lane >= o) {
+      ia += ua;
+      ib += ub;
+    }
+  }
+  __syncthreads();
+  if (lane == 63) {
+    sa[w] = ia;
+    sb[w] = ib;
+  }
+  __syncthreads();
+  int64_t ba = 0, bb = 0;
+  for (int i = 0; i < w; ++i) {
+    ba += sa[i];
+    bb += sb[i];
+  }
+  a = ba + ia - a;
+  b = bb + ib - b;
+}
+
+// One pass of the workgroup radix select after its histogram is complete:
+// the first wavefront reads the 256 bins (lane l: bins 255 - 4l .. 252 - 4l,
+// so lane order is descending bin order and one DPP scan over lanes counts
+// the values above each bin), clears them for the next pass, and writes the
+// selected digit and the count still needed to sel_sh.
+__device__ __forceinline__ void radix_select_digit_wave(int32_t* hist, int64_t need, int64_t* sel_sh) {
+  const int lane = threadIdx.x & 63;
+  int32_t c[4], tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    c[k] = hist[255 - 4 * lane - k];
+    hist[255 - 4 * lane - k] = 0;
+    tot += c[k];
+  }
+  int64_t above = wave_incl_scan_dpp(tot) - tot;
+  int sel = -1;
+  int64_t nn = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t ai = above + c[k];
+    if (sel < 0 && ai >= need && ai - c[k] < need) {
+      sel = 255 - 4 * lane - k;
+      nn = need - (ai - c[k]);
+    }
+    above = ai;
+  }
+  const uint64_t m = __ballot(sel >= 0);
+  if (m == 0) {
+    if (lane == 0) {
+      sel_sh[0] = 0;
+      sel_sh[1] = need;
+    }
+  } else if (lane == __ffsll((unsigned long long)m) - 1) {
+    sel_sh[0] = sel;
+    sel_sh[1] = nn;
+  }
+}
+
 // The radix select of tau and need (8 bits a pass, from the top) over one
 // wavefront's values val[j] >= 0 (negative: not taking part), each counting
 // cnt[j]: tau is the value at which the count of larger values stays below
@@ -650,7 +737,7 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
                                                         int64_t* __restrict__ off_all,
                                                         int32_t* __restrict__ ap_tab) {
   constexpr int kThreads = 1024, kWaves = kThreads / 64, kPerBin = kApBins / kThreads;
-  __shared__ int64_t sh64[kWaves];
+  __shared__ int64_t sh64[kWaves], sh64b[kWaves];
   __shared__ int32_t hist[256];
   __shared__ int64_t sel_sh[2];
   __shared__ int32_t H[kApBins];    // blocks per weight
@@ -746,8 +833,9 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
       sw += (int64_t)H[b] * b;
       na += H[b];
     }
-    S = group_sum<kWaves>(sw, sh64);
-    const int64_t A = group_sum<kWaves>(na, sh64);
+    group_sum2<kWaves>(sw, na, sh64, sh64b);
+    S = sw;
+    const int64_t A = na;
     if (A == 0) break;
     uniform = (S == 0);
     if (uniform) {
@@ -770,7 +858,9 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
     P -= cap * nc;
   }
 
-  // floors and remainders per open weight
+  // floors and remainders per open weight (and the radix select's bins
+  // cleared: each of its passes leaves them so)
+  if (tid < 256) hist[tid] = 0;
   int64_t sq = 0;
   for (int b = tid; b < nbins; b += kThreads) {
     int32_t rm = -1;
@@ -789,8 +879,6 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
   if (R > 0 && S > 1) {
     const int bits = 64 - __clzll((unsigned long long)(S - 1));
     for (int shift = ((bits + 7) / 8) * 8 - 8; shift >= 0; shift -= 8) {
-      if (tid < 256) hist[tid] = 0;
-      __syncthreads();
       const uint64_t hi_mask = (shift + 8 >= 64) ? 0ull : (~0ull << (shift + 8));
 #pragma unroll
       for (int j = 0; j < kPerBin; ++j) {
@@ -800,20 +888,10 @@ __global__ __launch_bounds__(1024) void k_apportion_hist(const ImgDev* __restric
           atomicAdd(&hist[((uint64_t)rm >> shift) & 255u], H[b]);
       }
       __syncthreads();
-      if (tid == 0) {
-        sel_sh[0] = 0;
-        sel_sh[1] = need;
-      }
-      const int32_t bin = tid < 256 ? hist[255 - tid] : 0;
-      const int64_t above_incl = group_exclusive_scan((int64_t)bin, sh64) + bin;
-      if (tid < 256 && above_incl >= need && above_incl - bin < need) {
-        sel_sh[0] = 255 - tid;
-        sel_sh[1] = need - (above_incl - bin);
-      }
+      if (tid < 64) radix_select_digit_wave(hist, need, sel_sh);
       __syncthreads();
       tau |= (int64_t)sel_sh[0] << shift;
       need = sel_sh[1];
-      __syncthreads();
     }
   }
 
@@ -1139,93 +1217,6 @@ struct ApportionLds {
   int32_t hist[256];
   int64_t sel_sh[2];
 };
-
-// Sums (or exclusive prefix sums in thread order) of two values over the
-// workgroup, with one pair of barriers for both.
-template <int NW>
-__device__ __forceinline__ void group_sum2(int64_t& a, int64_t& b, int64_t* sa, int64_t* sb) {
-  a = wave_sum_t(a);
-  b = wave_sum_t(b);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    sa[w] = a;
-    sb[w] = b;
-  }
-  __syncthreads();
-  a = 0;
-  b = 0;
-#pragma unroll
-  for (int i = 0; i < NW; ++i) {
-    a += sa[i];
-    b += sb[i];
-  }
-}
-
-template <int NW>
-__device__ __forceinline__ void group_exclusive_scan2(int64_t& a, int64_t& b, int64_t* sa, int64_t* sb) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int64_t ia = a, ib = b;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int64_t ua = __shfl_up(ia, o, 64), ub = __shfl_up(ib, o, 64);
-    if (lane >= o) {
-      ia += ua;
-      ib += ub;
-    }
-  }
-  __syncthreads();
-  if (lane == 63) {
-    sa[w] = ia;
-    sb[w] = ib;
-  }
-  __syncthreads();
-  int64_t ba = 0, bb = 0;
-  for (int i = 0; i < w; ++i) {
-    ba += sa[i];
-    bb += sb[i];
-  }
-  a = ba + ia - a;
-  b = bb + ib - b;
-}
-
-// One pass of the workgroup radix select after its histogram is complete:
-// the first wavefront reads the 256 bins (lane l: bins 255 - 4l .. 252 - 4l,
-// so lane order is descending bin order and one DPP scan over lanes counts
-// the values above each bin), clears them for the next pass, and writes the
-// selected digit and the count still needed to sel_sh.
-__device__ __forceinline__ void radix_select_digit_wave(int32_t* hist, int64_t need, int64_t* sel_sh) {
-  const int lane = threadIdx.x & 63;
-  int32_t c[4], tot = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    c[k] = hist[255 - 4 * lane - k];
-    hist[255 - 4 * lane - k] = 0;
-    tot += c[k];
-  }
-  int64_t above = wave_incl_scan_dpp(tot) - tot;
-  int sel = -1;
-  int64_t nn = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int64_t ai = above + c[k];
-    if (sel < 0 && ai >= need && ai - c[k] < need) {
-      sel = 255 - 4 * lane - k;
-      nn = need - (ai - c[k]);
-    }
-    above = ai;
-  }
-  const uint64_t m = __ballot(sel >= 0);
-  if (m == 0) {
-    if (lane == 0) {
-      sel_sh[0] = 0;
-      sel_sh[1] = need;
-    }
-  } else if (lane == __ffsll((unsigned long long)m) - 1) {
-    sel_sh[0] = sel;
-    sel_sh[1] = nn;
-  }
-}
 
 template <int kThreads, int kPer>
 __device__ __forceinline__ void apportion_image_reg(const ImgDev& im, int32_t* __restrict__ stat_all,
